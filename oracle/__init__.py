@@ -1,0 +1,169 @@
+"""CPU oracle of the displace+render frame (test infrastructure).
+
+TEST INFRASTRUCTURE: only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package. The GPU library never
+loads it and shares no code with it.
+
+The oracle is plain C (``mm_oracle.c``), built with gcc and FP contraction
+off; this module builds it on demand and wraps it for numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mm_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+          "-fexcess-precision=standard", "-fPIC", "-shared", "-Wall", "-Wextra"]
+EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (also called by the package build)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
+            os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "mm_oracle.h"))):
+        tmp = LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        u32p, u64p, f32p = (C.POINTER(C.c_uint32), C.POINTER(C.c_uint64),
+                            C.POINTER(C.c_float))
+        L.oracle_philox4x32_10_many.argtypes = [u32p, u32p, u32p, C.c_uint64]
+        L.oracle_offset.argtypes = [C.c_uint32, C.c_float]
+        L.oracle_offset.restype = C.c_float
+        L.oracle_offset_many.argtypes = [u32p, C.c_uint64, C.c_float, f32p]
+        L.oracle_wrap.argtypes = [C.c_float]
+        L.oracle_wrap.restype = C.c_float
+        L.oracle_displace.argtypes = [f32p, C.c_uint64, C.c_uint32, C.c_uint64,
+                                      C.c_uint32, C.c_float, C.c_int]
+        L.oracle_project.argtypes = [f32p, C.c_uint32, f32p, C.c_uint32, C.c_uint32,
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int32), u32p]
+        L.oracle_project.restype = C.c_int
+        L.oracle_splat.argtypes = [f32p, C.c_uint64, C.c_uint32, f32p, C.c_uint32,
+                                   C.c_uint32, C.c_uint32, u64p, u64p]
+        L.oracle_colour.argtypes = [C.c_uint32, C.c_uint64]
+        L.oracle_colour.restype = C.c_uint32
+        L.oracle_resolve.argtypes = [u64p, u32p, C.c_uint64, C.c_uint64]
+        L.oracle_step_render.argtypes = [f32p, C.c_uint64, C.c_uint32, C.c_uint64,
+                                         C.c_uint32, C.c_float, C.c_int, f32p,
+                                         C.c_uint32, C.c_uint32, C.c_uint32, u64p, u32p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _mat(m) -> np.ndarray:
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(16))
+    return m
+
+
+def philox4x32_10(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    """ctr (n, 4) uint32, key (n, 2) uint32 -> (n, 4) uint32."""
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, dtype=np.uint32).reshape(-1, 2)
+    assert ctr.shape[0] == key.shape[0]
+    out = np.empty_like(ctr)
+    lib().oracle_philox4x32_10_many(_ptr(ctr, C.c_uint32), _ptr(key, C.c_uint32),
+                                    _ptr(out, C.c_uint32), ctr.shape[0])
+    return out
+
+
+def offset(r: int, a: float) -> float:
+    return lib().oracle_offset(r, a)
+
+
+def offset_many(r: np.ndarray, a: float) -> np.ndarray:
+    r = np.ascontiguousarray(r, dtype=np.uint32)
+    out = np.empty(r.shape, dtype=np.float32)
+    lib().oracle_offset_many(_ptr(r, C.c_uint32), r.size, a, _ptr(out, C.c_float))
+    return out
+
+
+def wrap(x: float) -> float:
+    return lib().oracle_wrap(x)
+
+
+def displace(pos: np.ndarray, seed: int, step: int, a: float, wrap: bool) -> None:
+    """In place on a C-contiguous float32 (n, dim) array."""
+    assert pos.dtype == np.float32 and pos.ndim == 2
+    lib().oracle_displace(_ptr(pos, C.c_float), pos.shape[0], pos.shape[1], seed,
+                          step, a, int(wrap))
+
+
+def project(p, m, width: int, height: int):
+    """Returns (px, py, depth_bits) or None when the point is culled."""
+    p = np.ascontiguousarray(np.asarray(p, dtype=np.float32).reshape(-1))
+    m = _mat(m)
+    px, py, bits = C.c_int32(), C.c_int32(), C.c_uint32()
+    ok = lib().oracle_project(_ptr(p, C.c_float), p.shape[0], _ptr(m, C.c_float),
+                              width, height, C.byref(px), C.byref(py), C.byref(bits))
+    return (px.value, py.value, bits.value) if ok else None
+
+
+def new_depth(width: int, height: int) -> np.ndarray:
+    return np.full(width * height, EMPTY, dtype=np.uint64)
+
+
+def splat(pos: np.ndarray, m, width: int, height: int, footprint: int,
+          depth: np.ndarray, order: np.ndarray | None = None) -> None:
+    assert pos.dtype == np.float32 and depth.dtype == np.uint64
+    m = _mat(m)
+    optr = None
+    if order is not None:
+        order = np.ascontiguousarray(order, dtype=np.uint64)
+        assert order.shape[0] == pos.shape[0]
+        optr = _ptr(order, C.c_uint64)
+    lib().oracle_splat(_ptr(pos, C.c_float), pos.shape[0], pos.shape[1], _ptr(m, C.c_float),
+                       width, height, footprint, _ptr(depth, C.c_uint64), optr)
+
+
+def colour(index: int, seed: int) -> int:
+    return lib().oracle_colour(index, seed)
+
+
+def resolve(depth: np.ndarray, seed: int) -> np.ndarray:
+    out = np.empty(depth.shape[0], dtype=np.uint32)
+    lib().oracle_resolve(_ptr(depth, C.c_uint64), _ptr(out, C.c_uint32), depth.shape[0], seed)
+    return out
+
+
+def step_render(pos: np.ndarray, seed: int, step: int, a: float, wrap: bool, m,
+                width: int, height: int, footprint: int,
+                depth: np.ndarray | None = None) -> np.ndarray:
+    """Displace pos in place with step, then render; returns the RGBA8 frame
+    as (height, width) uint32."""
+    if depth is None:
+        depth = new_depth(width, height)
+    m = _mat(m)
+    out = np.empty(width * height, dtype=np.uint32)
+    lib().oracle_step_render(_ptr(pos, C.c_float), pos.shape[0], pos.shape[1], seed, step,
+                             a, int(wrap), _ptr(m, C.c_float), width, height, footprint,
+                             _ptr(depth, C.c_uint64), _ptr(out, C.c_uint32))
+    return out.reshape(height, width)
+
+
+def render(pos: np.ndarray, seed: int, m, width: int, height: int,
+           footprint: int) -> np.ndarray:
+    """Splat + resolve without displacement."""
+    depth = new_depth(width, height)
+    splat(pos, m, width, height, footprint, depth)
+    return resolve(depth, seed).reshape(height, width)
