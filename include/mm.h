@@ -1,0 +1,167 @@
+/*
+ * mm.h: C ABI of the MI355X displace+render library.
+ *
+ * The calls follow the three stages the Mimir paper gives its interface
+ * (section "Interface"): initialise an instance and allocate memory from it,
+ * describe a view of that memory, and render. Allocation mirrors the paper's
+ * allocLinear, which takes the same arguments as the native allocator and
+ * hands back a plain device pointer plus a handle (section "Allocations").
+ * A view is described by a plain struct, as the paper's ViewDescription
+ * (section "Views", listing "C++ Library usage example"): the position
+ * source, element count, format, domain, and here also the camera, the
+ * screen and the per-step displacement of the benchmark (section
+ * "Performance Benchmark"). There is no window and no graphics API: frames
+ * stay in device memory and are copied to the host only on request.
+ *
+ * Conventions for every call:
+ *  - The return value is an mm_status: MM_OK (0) or a negative error code.
+ *    On error, out-parameters are left untouched and mm_last_error() gives
+ *    a thread-local message.
+ *  - Pointers named dev_* are device addresses; every other pointer is host
+ *    memory owned by the caller and only read or written during the call.
+ *  - Calls on one instance (and on its views, batches) must be serialised
+ *    by the caller. The server object (mm_server_*) is internally locked.
+ *  - All device work is enqueued on the instance's stream, in call order.
+ *    Calls return without waiting unless stated ("synchronises").
+ *  - Positions are AoS float32: float2 (x, y) or float3 (x, y, z).
+ *  - Frames are RGBA8 packed in uint32 little-endian (R in the low byte),
+ *    row-major, row 0 = top of the screen; 0 = background.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_instance_s* mm_instance;
+typedef struct mm_alloc_s* mm_alloc;
+typedef struct mm_view_s* mm_view;
+
+typedef int32_t mm_status;
+#define MM_OK 0
+#define MM_ERR_INVALID_ARG (-1)   /* a null handle/pointer or an out-of-range field */
+#define MM_ERR_OUT_OF_MEMORY (-2) /* device or host allocation failed */
+#define MM_ERR_HIP (-3)           /* a HIP runtime call failed (message has the call) */
+#define MM_ERR_BUDGET (-4)        /* a request exceeds a configured memory budget */
+#define MM_ERR_IN_USE (-5)        /* the object is still referenced (e.g. alloc by a view) */
+#define MM_ERR_UNSUPPORTED (-6)   /* valid but not supported (format/domain combination) */
+#define MM_ERR_NOT_READY (-7)     /* a polled result is not available yet */
+
+typedef enum { MM_FLOAT2 = 2, MM_FLOAT3 = 3 } mm_format;
+typedef enum { MM_DOMAIN_2D = 2, MM_DOMAIN_3D = 3 } mm_domain;
+
+/* ---------------------------------------------------------------- instance
+ * Section "Initialization": the instance binds one device. Here it also
+ * binds one stream. */
+typedef struct {
+    int32_t device; /* HIP device ordinal */
+    void* stream;   /* hipStream_t to enqueue on (e.g. torch's current stream); NULL:
+                       the library creates a default-priority stream and owns it */
+} mm_instance_desc;
+
+/* Creates an instance on desc->device. *out receives the handle. */
+mm_status mm_create_instance(const mm_instance_desc* desc, mm_instance* out);
+
+/* Waits for the stream, destroys every view still alive, frees every
+ * allocation the instance owns (not wrapped ones), then the stream if it
+ * owns it. The handle is invalid afterwards. */
+mm_status mm_destroy_instance(mm_instance inst);
+
+/* Waits until all work enqueued on the instance's stream has finished. */
+mm_status mm_synchronize(mm_instance inst);
+
+/* ------------------------------------------------------------- allocations
+ * Section "Allocations": allocLinear takes the native allocator's
+ * arguments and returns a plain device pointer that kernels use as usual,
+ * plus a handle that views refer to. */
+
+/* Allocates bytes (> 0) of device memory owned by the instance, 256-byte
+ * aligned. *dev_ptr receives the device address, *out the handle. */
+mm_status mm_alloc_linear(mm_instance inst, size_t bytes, void** dev_ptr, mm_alloc* out);
+
+/* Wraps caller-owned device memory (e.g. a torch CUDA/HIP tensor) of
+ * `bytes` bytes at dev_ptr (4-byte aligned, on the instance's device). The
+ * library never frees it; the caller keeps it alive while views use it. */
+mm_status mm_alloc_wrap(mm_instance inst, void* dev_ptr, size_t bytes, mm_alloc* out);
+
+/* Releases the handle (and the memory, for mm_alloc_linear). Returns
+ * MM_ERR_IN_USE while a view still refers to it. */
+mm_status mm_free(mm_alloc alloc);
+
+/* ------------------------------------------------------------------- views
+ * Section "Views": a view describes how raw memory is drawn. Here a view
+ * draws a point cloud as markers of one size (section "Performance
+ * Benchmark": every point the same size), and also carries the benchmark's
+ * per-timestep displacement of that cloud. */
+typedef struct {
+    mm_alloc position;      /* source of the positions: element_count points, AoS */
+    uint64_t element_count; /* N, 1 <= N <= 2^32 - 1; N * stride must fit the alloc */
+    mm_format format;       /* MM_FLOAT2 with MM_DOMAIN_2D, MM_FLOAT3 with MM_DOMAIN_3D */
+    mm_domain domain;
+    uint32_t width;         /* screen size in pixels, each even and in [2, 16384] */
+    uint32_t height;
+    uint32_t footprint;     /* marker side in pixels: 1 or 3 */
+    uint64_t seed;          /* key of the displacement draw and of the colour hash */
+    float amplitude;        /* per-coordinate offset is uniform on [-a, a); a == 0 or
+                               2^-64 <= a <= 2^64 (a <= 1 when wrap is set) */
+    int32_t wrap;           /* 1: fold each coordinate into [-1, 1) after the step */
+    float view_proj[16];    /* row-major float32 clip-from-world matrix; 3D only */
+} mm_view_desc;
+
+/* Creates a view: validates desc, allocates its depth buffer (8 B per
+ * pixel, all empty) and its RGBA8 frame (4 B per pixel), and builds its
+ * per-frame graph. The view refers to desc->position until destroyed. */
+mm_status mm_create_view(mm_instance inst, const mm_view_desc* desc, mm_view* out);
+
+/* Frees the view's buffers and graph (after the stream has drained). */
+mm_status mm_destroy_view(mm_view view);
+
+/* Replaces the view's 3D camera (row-major, 16 floats) for later frames. */
+mm_status mm_set_camera(mm_view view, const float view_proj[16]);
+
+/* Displacement only: every point i moves by the draw keyed by (seed, i,
+ * step), as the benchmark's per-timestep kernel. */
+mm_status mm_step(mm_view view, uint32_t step);
+
+/* Render only: splat the current positions and resolve them into the
+ * view's frame (the depth buffer is left empty again). */
+mm_status mm_render(mm_view view);
+
+/* One frame: displace with `step`, then splat and resolve, as one graph
+ * launch on the stream. Equivalent to mm_step then mm_render. */
+mm_status mm_step_render(mm_view view, uint32_t step);
+
+/* *dev_rgba receives the device address of the view's frame (width *
+ * height uint32). It stays valid until the view is destroyed; its content
+ * is that of the last frame in stream order. */
+mm_status mm_frame_device_ptr(mm_view view, const uint32_t** dev_rgba);
+
+/* Copies the frame to host memory (bytes >= width * height * 4) after all
+ * enqueued work. Synchronises. */
+mm_status mm_read_frame(mm_view view, void* host_rgba, size_t bytes);
+
+/* Per-kernel timing of the next frames, for measurement. mm_profile_begin
+ * makes the view's next `capacity` calls of mm_step_render record HIP
+ * events around the splat and the resolve kernels, inside the frame graph.
+ * mm_profile_end synchronises and writes, per recorded frame k, the splat
+ * kernel time splat_ms[k], the resolve kernel time resolve_ms[k] and the
+ * whole frame graph frame_ms[k] (arrays of `capacity`, any may be NULL),
+ * and *count; recording then stops. */
+mm_status mm_profile_begin(mm_view view, uint32_t capacity);
+mm_status mm_profile_end(mm_view view, float* splat_ms, float* resolve_ms, float* frame_ms,
+                         uint32_t* count);
+
+/* ------------------------------------------------------------ diagnostics */
+const char* mm_status_string(mm_status status);
+const char* mm_last_error(void);
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t mm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

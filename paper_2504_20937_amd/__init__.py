@@ -1,0 +1,244 @@
+"""Python binding of libmm (the MI355X displace+render library).
+
+A thin ctypes layer over the C ABI declared in ``include/mm.h``: the same
+function names, arguments marshalled, errors raised as ``MMError``. Every
+step of the frame runs in the library's HIP kernels; this module computes
+nothing. Device memory and streams may come from PyTorch (pass
+``tensor.data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``), but
+this module does not import torch.
+
+The shared library must have been built (``python -m
+paper_2504_20937_amd.build`` or ``__graft_entry__.build()``); importing the
+binding without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmm.so")
+
+MM_OK = 0
+MM_ERR_INVALID_ARG = -1
+MM_ERR_OUT_OF_MEMORY = -2
+MM_ERR_HIP = -3
+MM_ERR_BUDGET = -4
+MM_ERR_IN_USE = -5
+MM_ERR_UNSUPPORTED = -6
+MM_ERR_NOT_READY = -7
+
+MM_FLOAT2 = 2
+MM_FLOAT3 = 3
+MM_DOMAIN_2D = 2
+MM_DOMAIN_3D = 3
+
+
+class MMError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {status_name(status)} ({status}): {detail}")
+        self.status = status
+
+
+class mm_instance_desc(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class mm_view_desc(C.Structure):
+    _fields_ = [
+        ("position", C.c_void_p),
+        ("element_count", C.c_uint64),
+        ("format", C.c_int),
+        ("domain", C.c_int),
+        ("width", C.c_uint32),
+        ("height", C.c_uint32),
+        ("footprint", C.c_uint32),
+        ("seed", C.c_uint64),
+        ("amplitude", C.c_float),
+        ("wrap", C.c_int32),
+        ("view_proj", C.c_float * 16),
+    ]
+
+
+_lib = None
+_status = C.c_int32
+_vp = C.c_void_p
+
+
+def _declare(L):
+    sig = {
+        "mm_version": ([], C.c_int32),
+        "mm_last_error": ([], C.c_char_p),
+        "mm_status_string": ([C.c_int32], C.c_char_p),
+        "mm_create_instance": ([C.POINTER(mm_instance_desc), C.POINTER(_vp)], _status),
+        "mm_destroy_instance": ([_vp], _status),
+        "mm_synchronize": ([_vp], _status),
+        "mm_alloc_linear": ([_vp, C.c_size_t, C.POINTER(_vp), C.POINTER(_vp)], _status),
+        "mm_alloc_wrap": ([_vp, _vp, C.c_size_t, C.POINTER(_vp)], _status),
+        "mm_free": ([_vp], _status),
+        "mm_create_view": ([_vp, C.POINTER(mm_view_desc), C.POINTER(_vp)], _status),
+        "mm_destroy_view": ([_vp], _status),
+        "mm_set_camera": ([_vp, C.POINTER(C.c_float)], _status),
+        "mm_step": ([_vp, C.c_uint32], _status),
+        "mm_render": ([_vp], _status),
+        "mm_step_render": ([_vp, C.c_uint32], _status),
+        "mm_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
+        "mm_read_frame": ([_vp, _vp, C.c_size_t], _status),
+        "mm_profile_begin": ([_vp, C.c_uint32], _status),
+        "mm_profile_end": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                            C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+
+
+def lib() -> C.CDLL:
+    """The loaded libmm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2504_20937_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def status_name(status: int) -> str:
+    return lib().mm_status_string(status).decode()
+
+
+def mm_last_error() -> str:
+    return lib().mm_last_error().decode()
+
+
+def mm_status_string(status: int) -> str:
+    return status_name(status)
+
+
+def mm_version() -> int:
+    return lib().mm_version()
+
+
+def _check(status: int, where: str) -> None:
+    if status != MM_OK:
+        raise MMError(status, where, mm_last_error())
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+# ------------------------------------------------------------------ instance
+def mm_create_instance(device: int = 0, stream: int | None = None) -> int:
+    desc = mm_instance_desc(device, stream or None)
+    out = _vp()
+    _check(lib().mm_create_instance(C.byref(desc), C.byref(out)), "mm_create_instance")
+    return out.value
+
+
+def mm_destroy_instance(inst: int) -> None:
+    _check(lib().mm_destroy_instance(inst), "mm_destroy_instance")
+
+
+def mm_synchronize(inst: int) -> None:
+    _check(lib().mm_synchronize(inst), "mm_synchronize")
+
+
+# --------------------------------------------------------------- allocations
+def mm_alloc_linear(inst: int, nbytes: int) -> tuple[int, int]:
+    """Returns (device pointer, alloc handle)."""
+    ptr, out = _vp(), _vp()
+    _check(lib().mm_alloc_linear(inst, nbytes, C.byref(ptr), C.byref(out)), "mm_alloc_linear")
+    return ptr.value, out.value
+
+
+def mm_alloc_wrap(inst: int, dev_ptr: int, nbytes: int) -> int:
+    out = _vp()
+    _check(lib().mm_alloc_wrap(inst, dev_ptr, nbytes, C.byref(out)), "mm_alloc_wrap")
+    return out.value
+
+
+def mm_free(alloc: int) -> None:
+    _check(lib().mm_free(alloc), "mm_free")
+
+
+# --------------------------------------------------------------------- views
+def make_view_desc(position: int, element_count: int, dim: int, width: int, height: int,
+                   footprint: int = 1, seed: int = 0, amplitude: float = 0.0,
+                   wrap: bool = False, view_proj=None) -> mm_view_desc:
+    d = mm_view_desc()
+    d.position = position
+    d.element_count = element_count
+    d.format = MM_FLOAT2 if dim == 2 else MM_FLOAT3
+    d.domain = MM_DOMAIN_2D if dim == 2 else MM_DOMAIN_3D
+    d.width, d.height, d.footprint = width, height, footprint
+    d.seed = seed
+    d.amplitude = amplitude
+    d.wrap = int(bool(wrap))
+    m = np.eye(4, dtype=np.float32) if view_proj is None else view_proj
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(16))
+    for k in range(16):
+        d.view_proj[k] = float(m[k])
+    return d
+
+
+def mm_create_view(inst: int, desc: mm_view_desc) -> int:
+    out = _vp()
+    _check(lib().mm_create_view(inst, C.byref(desc), C.byref(out)), "mm_create_view")
+    return out.value
+
+
+def mm_destroy_view(view: int) -> None:
+    _check(lib().mm_destroy_view(view), "mm_destroy_view")
+
+
+def mm_set_camera(view: int, view_proj) -> None:
+    m = np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(16))
+    _check(lib().mm_set_camera(view, _fptr(m)), "mm_set_camera")
+
+
+def mm_step(view: int, step: int) -> None:
+    _check(lib().mm_step(view, step), "mm_step")
+
+
+def mm_render(view: int) -> None:
+    _check(lib().mm_render(view), "mm_render")
+
+
+def mm_step_render(view: int, step: int) -> None:
+    _check(lib().mm_step_render(view, step), "mm_step_render")
+
+
+def mm_frame_device_ptr(view: int) -> int:
+    out = _vp()
+    _check(lib().mm_frame_device_ptr(view, C.byref(out)), "mm_frame_device_ptr")
+    return out.value
+
+
+def mm_read_frame(view: int, width: int, height: int) -> np.ndarray:
+    """The view's RGBA8 frame as a (height, width) uint32 array (synchronises)."""
+    out = np.empty((height, width), dtype=np.uint32)
+    _check(lib().mm_read_frame(view, out.ctypes.data, out.nbytes), "mm_read_frame")
+    return out
+
+
+def mm_profile_begin(view: int, capacity: int) -> None:
+    _check(lib().mm_profile_begin(view, capacity), "mm_profile_begin")
+
+
+def mm_profile_end(view: int, capacity: int):
+    """Returns (splat_ms, resolve_ms, frame_ms) float32 arrays of the recorded frames."""
+    s = np.zeros(capacity, dtype=np.float32)
+    r = np.zeros(capacity, dtype=np.float32)
+    f = np.zeros(capacity, dtype=np.float32)
+    n = C.c_uint32()
+    _check(lib().mm_profile_end(view, _fptr(s), _fptr(r), _fptr(f), C.byref(n)),
+           "mm_profile_end")
+    k = n.value
+    return s[:k], r[:k], f[:k]

@@ -1,0 +1,275 @@
+"""GPU parity: positions and frames from the HIP path through the C ABI must
+equal the CPU oracle bit for bit (the frame is the unique min over a total
+order of keys, and positions follow a deterministic binary32 recurrence)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import Rig, first_diff, hip, same_bits, say, HIP_D2H, HIP_H2D
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    return torch
+
+
+@pytest.fixture
+def rig(torch_gpu):
+    r = Rig()
+    yield r
+    r.close()
+
+
+def _run(rig, pts, dim, w, h, foot, seed, amp, wrap, frames, cam_fn, check_every=1,
+         split=False):
+    mm = rig.mm
+    n = pts.shape[0]
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, n, dim, w, h, foot, seed, amp, wrap, cam_fn(0))
+    ref = pts.copy()
+    for s in range(frames):
+        cam = cam_fn(s)
+        mm.mm_set_camera(view, cam)
+        if split:
+            mm.mm_step(view, s)
+            mm.mm_render(view)
+        else:
+            mm.mm_step_render(view, s)
+        want = oracle.step_render(ref, seed, s, amp, wrap, cam, w, h, foot)
+        if s % check_every == 0 or s == frames - 1:
+            got = mm.mm_read_frame(view, w, h)
+            assert np.array_equal(got, want), f"frame {s}: {first_diff(got, want)}"
+            pos = rig.positions(dev)
+            assert same_bits(pos, ref), f"positions after step {s}: {first_diff(pos, ref)}"
+    mm.mm_destroy_view(view)
+    mm.mm_free(alloc)
+    return ref
+
+
+def test_2d_65536_points_512sq_100_steps(rig):
+    say("case: 2D uniform, 65536 points, 512x512, a=0.005, wrap, 100 steps, every step")
+    pts = synth.uniform_square(65536, seed=0)
+    _run(rig, pts, 2, 512, 512, 1, 0, 0.005, True, 100, lambda s: synth.IDENTITY)
+
+
+def test_3d_uniform_ragged_small(rig):
+    say("case: 3D uniform, 65613 points (ragged), 320x240, 12 frames")
+    pts = synth.uniform_cube(65536 + 77, seed=3)
+    _run(rig, pts, 3, 320, 240, 1, 3, 0.001, False, 12,
+         lambda s: synth.orbit_camera(s, 320, 240))
+
+
+def test_3d_split_step_render_matches(rig):
+    say("case: 3D uniform, mm_step + mm_render, 30001 points, 200x100, 5 frames")
+    pts = synth.uniform_cube(30001, seed=4)
+    _run(rig, pts, 3, 200, 100, 1, 4, 0.001, False, 5,
+         lambda s: synth.orbit_camera(3 * s, 200, 100), split=True)
+
+
+def test_3d_footprint3_mixture(rig):
+    say("case: 3D mixture sigma 0.02, 3x3 footprint, 2^18 points, 640x360, 4 frames")
+    pts = synth.gaussian_mixture(1 << 18, seed=0)
+    _run(rig, pts, 3, 640, 360, 3, 0, 0.001, False, 4,
+         lambda s: synth.orbit_camera(s, 640, 360))
+
+
+def test_2d_footprint3_ties(rig):
+    say("case: 2D grid points with heavy ties, 3x3 footprint, 20000 points, 64x64")
+    rng = np.random.default_rng(0)
+    pts = (rng.integers(-32, 32, size=(20000, 2)) / 32.0).astype(np.float32)
+    _run(rig, pts, 2, 64, 64, 3, 9, 0.0, False, 2, lambda s: synth.IDENTITY)
+
+
+def test_3d_2p20_points_1080p(rig):
+    say("case: 3D uniform, 2^20 points, 1920x1080, 3 frames")
+    pts = synth.uniform_cube(1 << 20, seed=0)
+    _run(rig, pts, 3, 1920, 1080, 1, 0, 0.001, False, 3,
+         lambda s: synth.orbit_camera(s, 1920, 1080))
+
+
+def test_3d_2p24_points_1080p_full_size(rig):
+    say("case: 3D uniform, 2^24 points, 1920x1080, 2 frames (full benchmark size)")
+    pts = synth.uniform_cube(1 << 24, seed=0)
+    _run(rig, pts, 3, 1920, 1080, 1, 0, 0.001, False, 2,
+         lambda s: synth.orbit_camera(s, 1920, 1080))
+
+
+def test_3d_mixture_4k_footprint3(rig):
+    say("case: 3D mixture, 2^22 points, 3840x2160, 3x3 footprint, 2 frames")
+    pts = synth.gaussian_mixture(1 << 22, seed=0)
+    _run(rig, pts, 3, 3840, 2160, 3, 0, 0.001, False, 2,
+         lambda s: synth.orbit_camera(s, 3840, 2160))
+
+
+@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 1025])
+def test_tiny_and_ragged_counts(rig, n):
+    say(f"case: 3D uniform, {n} points, 16x8 and 2D {n} points 8x8")
+    _run(rig, synth.uniform_cube(n, seed=n), 3, 16, 8, 3, n, 0.001, False, 3,
+         lambda s: synth.orbit_camera(10 * s, 16, 8))
+    _run(rig, synth.uniform_square(n, seed=n), 2, 8, 8, 1, n, 0.005, True, 3,
+         lambda s: synth.IDENTITY)
+
+
+def test_smallest_screen_and_everything_culled(rig):
+    say("case: 2x2 screen; camera looking away (all culled)")
+    pts = synth.uniform_cube(4096, seed=1)
+    _run(rig, pts, 3, 2, 2, 3, 1, 0.001, False, 2, lambda s: synth.orbit_camera(s, 2, 2))
+    away = synth.look_at_perspective((0.5, 0.5, 3.0), (0.5, 0.5, 6.0), (0, 1, 0), 60.0, 1.0)
+    mm = rig.mm
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, 4096, 3, 32, 32, 1, 1, 0.001, False, away)
+    mm.mm_step_render(view, 0)
+    assert not mm.mm_read_frame(view, 32, 32).any()
+
+
+def test_2d_points_on_pixel_edges_and_borders(rig):
+    say("case: 2D points on pixel edges, corners and just inside/outside the box")
+    w, h = 64, 32
+    xs = np.array([-1.0, 1.0 - 2.0**-23, 1.0 - 2.0**-24, 0.0, -0.5, 2.0 / 64 - 1.0],
+                  dtype=np.float32)
+    pts = np.array([[x, y] for x in xs for y in xs], dtype=np.float32)
+    _run(rig, pts, 2, w, h, 3, 5, 0.0, False, 1, lambda s: synth.IDENTITY)
+
+
+def test_view_sharing_one_cloud(rig):
+    say("case: two views over one cloud: one steps, the other renders only")
+    mm = rig.mm
+    pts = synth.uniform_cube(50000, seed=2)
+    dev, alloc = rig.cloud(pts)
+    va = rig.view(alloc, 50000, 3, 160, 120, 1, 2, 0.001, False, synth.orbit_camera(0, 160, 120))
+    camb = synth.orbit_camera(90, 256, 256)
+    vb = rig.view(alloc, 50000, 3, 256, 256, 3, 2, 0.001, False, camb)
+    ref = pts.copy()
+    for s in range(3):
+        mm.mm_step_render(va, s)
+        mm.mm_render(vb)
+        fa = oracle.step_render(ref, 2, s, 0.001, False, synth.orbit_camera(0, 160, 120),
+                                160, 120, 1)
+        assert np.array_equal(mm.mm_read_frame(va, 160, 120), fa)
+        assert np.array_equal(mm.mm_read_frame(vb, 256, 256),
+                              oracle.render(ref, 2, camb, 256, 256, 3))
+    with pytest.raises(mm.MMError) as e:
+        mm.mm_free(alloc)
+    assert e.value.status == mm.MM_ERR_IN_USE
+    mm.mm_destroy_view(va)
+    mm.mm_destroy_view(vb)
+    mm.mm_free(alloc)
+
+
+def test_alloc_linear_owned_memory(rig):
+    say("case: mm_alloc_linear memory, host copies through hipMemcpy")
+    mm = rig.mm
+    n = 10007
+    pts = synth.uniform_cube(n, seed=12)
+    ptr, alloc = mm.mm_alloc_linear(rig.inst, n * 12)
+    assert ptr % 256 == 0
+    H = hip()
+    assert H.hipMemcpy(ptr, pts.ctypes.data, n * 12, HIP_H2D) == 0
+    cam = synth.orbit_camera(7, 128, 96)
+    view = rig.view(alloc, n, 3, 128, 96, 1, 12, 0.001, False, cam)
+    mm.mm_step_render(view, 0)
+    ref = pts.copy()
+    want = oracle.step_render(ref, 12, 0, 0.001, False, cam, 128, 96, 1)
+    assert np.array_equal(mm.mm_read_frame(view, 128, 96), want)
+    back = np.empty_like(pts)
+    assert H.hipMemcpy(back.ctypes.data, ptr, n * 12, HIP_D2H) == 0
+    assert same_bits(back, ref)
+    mm.mm_destroy_view(view)
+    mm.mm_free(alloc)
+
+
+def test_resume_from_snapshot(rig):
+    say("case: checkpoint at step 50 of the 2D workload and resume")
+    mm = rig.mm
+    pts = synth.uniform_square(65536, seed=0)
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, 65536, 2, 512, 512, 1, 0, 0.005, True)
+    for s in range(50):
+        mm.mm_step_render(view, s)
+    snap = rig.positions(dev).copy()
+    dev2, alloc2 = rig.cloud(snap)
+    view2 = rig.view(alloc2, 65536, 2, 512, 512, 1, 0, 0.005, True)
+    for s in range(50, 60):
+        mm.mm_step_render(view, s)
+        mm.mm_step_render(view2, s)
+        assert np.array_equal(mm.mm_read_frame(view, 512, 512), mm.mm_read_frame(view2, 512, 512))
+    assert same_bits(rig.positions(dev), rig.positions(dev2))
+
+
+def test_profile_records_kernel_times(rig):
+    say("case: mm_profile_begin/end around 20 frames, 2^20 points 1080p")
+    mm = rig.mm
+    pts = synth.uniform_cube(1 << 20, seed=0)
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, 1 << 20, 3, 1920, 1080, 1, 0, 0.001, False,
+                    synth.orbit_camera(0, 1920, 1080))
+    mm.mm_profile_begin(view, 20)
+    ref = pts.copy()
+    for s in range(25):  # 5 beyond capacity run untimed
+        mm.mm_set_camera(view, synth.orbit_camera(s, 1920, 1080))
+        mm.mm_step_render(view, s)
+    sp, rs, fr = mm.mm_profile_end(view, 20)
+    assert sp.shape == (20,) and np.all(sp > 0) and np.all(rs > 0)
+    assert np.all(fr >= sp) and np.all(fr >= rs)
+    # the timed graph computes the same frames
+    for s in range(25):
+        want = oracle.step_render(ref, 0, s, 0.001, False, synth.orbit_camera(s, 1920, 1080),
+                                  1920, 1080, 1)
+    assert np.array_equal(mm.mm_read_frame(view, 1920, 1080), want)
+    assert same_bits(rig.positions(dev), ref)
+
+
+def test_invalid_descriptions_are_rejected(rig):
+    say("case: invalid view descriptions and wraps")
+    mm = rig.mm
+    pts = synth.uniform_cube(1000, seed=0)
+    dev, alloc = rig.cloud(pts)
+    base = dict(alloc=alloc, n=1000, dim=3, w=64, h=64)
+
+    def expect(status, **kw):
+        args = {**base, **kw}
+        with pytest.raises(mm.MMError) as e:
+            rig.view(args["alloc"], args["n"], args["dim"], args["w"], args["h"],
+                     kw.get("foot", 1), 0, kw.get("amp", 0.001), kw.get("wrap", False))
+        assert e.value.status == status, str(e.value)
+
+    expect(mm.MM_ERR_INVALID_ARG, n=1001)          # overruns the alloc
+    expect(mm.MM_ERR_INVALID_ARG, n=0)
+    expect(mm.MM_ERR_INVALID_ARG, w=63)            # odd width
+    expect(mm.MM_ERR_INVALID_ARG, h=0)
+    expect(mm.MM_ERR_INVALID_ARG, w=16386)
+    expect(mm.MM_ERR_INVALID_ARG, foot=2)
+    expect(mm.MM_ERR_INVALID_ARG, amp=float("nan"))
+    expect(mm.MM_ERR_INVALID_ARG, amp=-0.001)
+    expect(mm.MM_ERR_INVALID_ARG, amp=2.0, wrap=True)
+    # float3 data described as 2D
+    d = mm.make_view_desc(alloc, 1000, 3, 64, 64)
+    d.domain = mm.MM_DOMAIN_2D
+    with pytest.raises(mm.MMError) as e:
+        mm.mm_create_view(rig.inst, d)
+    assert e.value.status == mm.MM_ERR_UNSUPPORTED
+    # wrapping more bytes than the device allocation holds (torch's caching
+    # allocator carves tensors out of larger segments, so overrun by far more
+    # than any segment)
+    with pytest.raises(mm.MMError) as e:
+        mm.mm_alloc_wrap(rig.inst, dev.data_ptr(), 1 << 40)
+    assert e.value.status == mm.MM_ERR_INVALID_ARG
+    # a host pointer is not device memory
+    host = np.zeros(16, dtype=np.float32)
+    with pytest.raises(mm.MMError):
+        mm.mm_alloc_wrap(rig.inst, host.ctypes.data, 64)
+    # a non-finite camera
+    view = rig.view(alloc, 1000, 3, 64, 64)
+    bad = np.eye(4, dtype=np.float32)
+    bad[0, 0] = np.inf
+    with pytest.raises(mm.MMError):
+        mm.mm_set_camera(view, bad)
+    with pytest.raises(mm.MMError):
+        mm.mm_read_frame(view, 32, 32)  # too small a host buffer
