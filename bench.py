@@ -59,6 +59,9 @@ def main() -> int:
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--cpu-frames", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--splat", choices=["auto", "direct", "binned"], default="auto")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--ppt", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -84,7 +87,14 @@ def main() -> int:
     alloc = mm.mm_alloc_wrap(inst, dev.data_ptr(), dev.numel() * 4)
     view = mm.mm_create_view(inst, mm.make_view_desc(alloc, n, 3, w, h, 1, 0, 0.001, False,
                                                      cams[0]))
-    print(f"bench: {n} points, {w}x{h}, warmup {W}, timed {K}", file=sys.stderr, flush=True)
+    splat = {"auto": mm.MM_SPLAT_AUTO, "direct": mm.MM_SPLAT_DIRECT,
+             "binned": mm.MM_SPLAT_BINNED}[args.splat]
+    if splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt:
+        mm.mm_set_tuning(view, splat, args.tile, args.ppt)
+    tuning = mm.mm_get_tuning(view)
+    mode = "direct" if tuning[0] == mm.MM_SPLAT_DIRECT else "binned"
+    print(f"bench: {n} points, {w}x{h}, warmup {W}, timed {K}, splat {mode} {tuning}",
+          file=sys.stderr, flush=True)
     for f in range(W):
         mm.mm_set_camera(view, cams[f])
         mm.mm_step_render(view, f)
@@ -122,15 +132,17 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"3d-uniform-2^{args.log2n}pts-{w}x{h}-orbit-1deg",
                    "points": n, "width": w, "height": h, "footprint": 1,
-                   "amplitude": 0.001, "graph": "one hipGraph per frame"},
+                   "amplitude": 0.001, "graph": "one hipGraph per frame",
+                   "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2]},
         "frames_per_s": K / elapsed,
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),
         "point_kernel_ms": splat_avg,
-        "resolve_kernel_ms": float(np.mean(resolve_ms)),
+        "rest_of_frame_ms": float(np.mean(resolve_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "point_kernel (displace+project+splat)",
+                     "kernel": ("bin_kernel (displace+project+tile sort)" if mode == "binned"
+                                else "point_kernel (displace+project+splat)"),
                      "bytes_per_launch": point_bytes},
         "frame_roofline": {"bytes_per_frame": frame_bytes,
                            "achieved_GBps": frame_bytes / (elapsed / K) / 1e9,

@@ -112,9 +112,10 @@ typedef struct {
     float view_proj[16];    /* row-major float32 clip-from-world matrix; 3D only */
 } mm_view_desc;
 
-/* Creates a view: validates desc, allocates its depth buffer (8 B per
- * pixel, all empty) and its RGBA8 frame (4 B per pixel), and builds its
- * per-frame graph. The view refers to desc->position until destroyed. */
+/* Creates a view: validates desc, allocates its RGBA8 frame (4 B per pixel,
+ * zero) and the scratch buffers of its splat strategy (MM_SPLAT_AUTO, see
+ * mm_set_tuning), and builds its per-frame graph. The view refers to
+ * desc->position until destroyed. */
 mm_status mm_create_view(mm_instance inst, const mm_view_desc* desc, mm_view* out);
 
 /* Frees the view's buffers and graph (after the stream has drained). */
@@ -128,7 +129,7 @@ mm_status mm_set_camera(mm_view view, const float view_proj[16]);
 mm_status mm_step(mm_view view, uint32_t step);
 
 /* Render only: splat the current positions and resolve them into the
- * view's frame (the depth buffer is left empty again). */
+ * view's frame. */
 mm_status mm_render(mm_view view);
 
 /* One frame: displace with `step`, then splat and resolve, as one graph
@@ -144,12 +145,42 @@ mm_status mm_frame_device_ptr(mm_view view, const uint32_t** dev_rgba);
  * enqueued work. Synchronises. */
 mm_status mm_read_frame(mm_view view, void* host_rgba, size_t bytes);
 
+/* Splat strategy of a view (all give the same frames, bit for bit).
+ *  MM_SPLAT_DIRECT: 64-bit atomicMin of each point's key into a full-screen
+ *    key buffer (skipped when a plain load already shows a smaller key),
+ *    then a resolve pass over the screen.
+ *  MM_SPLAT_BINNED: each workgroup sorts its points by screen tile in LDS
+ *    and writes 8-byte records; then one workgroup per tile takes the
+ *    per-pixel minimum in LDS and writes RGBA8 directly (3x3 footprints
+ *    merge tile seams in a third pass). No global atomics.
+ *  MM_SPLAT_AUTO: binned when the screen fits the tile table, else direct. */
+#define MM_SPLAT_AUTO 0u
+#define MM_SPLAT_DIRECT 1u
+#define MM_SPLAT_BINNED 2u
+
+typedef struct {
+    uint32_t splat;             /* MM_SPLAT_* */
+    uint32_t tile;              /* binned tile side: 16, 32 or 64 pixels; 0 = auto */
+    uint32_t points_per_thread; /* binned: 4, 8 or 16 (workgroup of 256 threads); 0 = auto */
+} mm_tuning;
+
+/* Chooses the splat strategy and its shape for later frames; reallocates the
+ * view's scratch buffers and rebuilds its graph. Synchronises. Returns
+ * MM_ERR_UNSUPPORTED for a shape the screen cannot use (e.g. more than 4096
+ * tiles). */
+mm_status mm_set_tuning(mm_view view, const mm_tuning* tuning);
+
+/* The resolved strategy and shape in use (never MM_SPLAT_AUTO or 0). */
+mm_status mm_get_tuning(mm_view view, mm_tuning* out);
+
 /* Per-kernel timing of the next frames, for measurement. mm_profile_begin
  * makes the view's next `capacity` calls of mm_step_render record HIP
- * events around the splat and the resolve kernels, inside the frame graph.
- * mm_profile_end synchronises and writes, per recorded frame k, the splat
- * kernel time splat_ms[k], the resolve kernel time resolve_ms[k] and the
- * whole frame graph frame_ms[k] (arrays of `capacity`, any may be NULL),
+ * events inside the frame graph: before and after the point pass (displace,
+ * project and splat or bin: the direct point kernel or the bin kernel) and
+ * after the last node. mm_profile_end synchronises and writes, per recorded
+ * frame k, the point pass time splat_ms[k], the time of the remaining
+ * passes (resolve, or tile + seam) resolve_ms[k] and the whole frame graph
+ * frame_ms[k] (arrays of `capacity`, any may be NULL),
  * and *count; recording then stops. */
 mm_status mm_profile_begin(mm_view view, uint32_t capacity);
 mm_status mm_profile_end(mm_view view, float* splat_ms, float* resolve_ms, float* frame_ms,

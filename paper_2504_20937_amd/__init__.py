@@ -32,6 +32,9 @@ MM_ERR_NOT_READY = -7
 
 MM_FLOAT2 = 2
 MM_FLOAT3 = 3
+MM_SPLAT_AUTO = 0
+MM_SPLAT_DIRECT = 1
+MM_SPLAT_BINNED = 2
 MM_DOMAIN_2D = 2
 MM_DOMAIN_3D = 3
 
@@ -62,6 +65,10 @@ class mm_view_desc(C.Structure):
     ]
 
 
+class mm_tuning(C.Structure):
+    _fields_ = [("splat", C.c_uint32), ("tile", C.c_uint32), ("points_per_thread", C.c_uint32)]
+
+
 _lib = None
 _status = C.c_int32
 _vp = C.c_void_p
@@ -86,6 +93,8 @@ def _declare(L):
         "mm_step_render": ([_vp, C.c_uint32], _status),
         "mm_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
         "mm_read_frame": ([_vp, _vp, C.c_size_t], _status),
+        "mm_set_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
+        "mm_get_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
         "mm_profile_begin": ([_vp, C.c_uint32], _status),
         "mm_profile_end": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
                             C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
@@ -196,6 +205,19 @@ def mm_create_view(inst: int, desc: mm_view_desc) -> int:
 
 def mm_destroy_view(view: int) -> None:
     _check(lib().mm_destroy_view(view), "mm_destroy_view")
+
+
+def mm_set_tuning(view: int, splat: int = MM_SPLAT_AUTO, tile: int = 0,
+                  points_per_thread: int = 0) -> None:
+    t = mm_tuning(splat, tile, points_per_thread)
+    _check(lib().mm_set_tuning(view, C.byref(t)), "mm_set_tuning")
+
+
+def mm_get_tuning(view: int) -> tuple[int, int, int]:
+    """(splat, tile, points_per_thread) in use."""
+    t = mm_tuning()
+    _check(lib().mm_get_tuning(view, C.byref(t)), "mm_get_tuning")
+    return t.splat, t.tile, t.points_per_thread
 
 
 def mm_set_camera(view: int, view_proj) -> None:

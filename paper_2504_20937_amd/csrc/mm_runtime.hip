@@ -1,18 +1,18 @@
 // C ABI runtime: instances, allocations, views and the per-frame graph.
 //
-// A frame is one hipGraph: [point kernel: displace+project+splat] ->
-// [resolve kernel: colour + clear]. The graph is built once per view; per
-// frame only the point kernel's argument block (step, camera) is replaced
-// with hipGraphExecKernelNodeSetParams before hipGraphLaunch, so a frame
-// costs two host calls and no host synchronisation.
+// A frame is one hipGraph. Direct splat: [point kernel: displace + project
+// + atomicMin] -> [resolve]. Binned splat: [bin kernel: displace + project +
+// LDS sort by tile] -> [tile kernel: LDS min + resolve] (-> [seam kernel] for
+// 3x3 footprints). The graph is built once per view (and per tuning); per
+// frame only the first node's argument block (step, camera, frame stamp) is
+// replaced with hipGraphExecKernelNodeSetParams before hipGraphLaunch, so a
+// frame costs two host calls and no host synchronisation.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -29,25 +29,40 @@ struct mm_alloc_s {
     uint32_t users;  // views referring to it
 };
 
+namespace {
+
+struct FrameGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t first = nullptr;                 // node whose arguments change per frame
+    hipGraphNode_t ev[3] = {nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+
 struct mm_view_s {
     mm_instance inst;
     mm_alloc position;
     mm_view_desc desc;
-    uint64_t* depth = nullptr;
+    mm_tuning tuning{};
     uint32_t* colour = nullptr;
+    // direct splat
+    uint64_t* depth = nullptr;
+    // binned splat
+    uint64_t* seg = nullptr;
+    uint16_t* table = nullptr;
+    uint32_t* active = nullptr;  // ntiles stamps + 1 slot for the frame stamp
+    uint64_t* border = nullptr;
+    uint64_t* apron = nullptr;
+    uint32_t tiles_x = 0, tiles_y = 0, ntiles = 0, num_wg = 0, stamp = 0;
+    // kernel arguments
     mm::PointArgs args{};
     mm::ResolveArgs rargs{};
-    // frame graph: plain, and a timed variant with event-record nodes
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t point_node = nullptr;
-    hipGraph_t tgraph = nullptr;
-    hipGraphExec_t texec = nullptr;
-    hipGraphNode_t tpoint_node = nullptr;
-    hipGraphNode_t tevent_node[3] = {nullptr, nullptr, nullptr};
-    mm::Launch point_l{}, resolve_l{};
-    // profiling ring
-    std::vector<hipEvent_t> events;  // 3 per frame
+    mm::BinArgs bargs{};
+    mm::TileArgs targs{};
+    std::vector<mm::Launch> nodes;  // frame graph kernels in order; [0] takes per-frame args
+    FrameGraph plain, timed;
+    std::vector<hipEvent_t> events;  // 3 per profiled frame
     uint32_t prof_cap = 0, prof_count = 0;
     bool profiling = false;
 };
@@ -74,6 +89,11 @@ mm_status fail(mm_status st, const char* fmt, ...) {
     return st;
 }
 
+mm_status hip_fail(hipError_t e, const char* what) {
+    return fail(e == hipErrorOutOfMemory ? MM_ERR_OUT_OF_MEMORY : MM_ERR_HIP, "%s failed: %s",
+                what, hipGetErrorString(e));
+}
+
 #define MM_HIP(call)                                                                        \
     do {                                                                                    \
         const hipError_t e_ = (call);                                                       \
@@ -81,6 +101,12 @@ mm_status fail(mm_status st, const char* fmt, ...) {
             return fail(e_ == hipErrorOutOfMemory ? MM_ERR_OUT_OF_MEMORY : MM_ERR_HIP,       \
                         "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
                         __LINE__);                                                          \
+    } while (0)
+
+#define MM_TRY(expr)                       \
+    do {                                   \
+        const mm_status s_ = (expr);       \
+        if (s_ != MM_OK) return s_;        \
     } while (0)
 
 struct DeviceGuard {
@@ -94,8 +120,18 @@ struct DeviceGuard {
     }
 };
 
-bool finite_positive_pow2_range(float a) {
-    return std::isfinite(a) && a >= 0x1p-64f && a <= 0x1p64f;
+bool amplitude_ok(float a) {
+    return a == 0.0f || (std::isfinite(a) && a >= 0x1p-64f && a <= 0x1p64f);
+}
+
+uint32_t shift_of(uint32_t side) {
+    return side == 16 ? 4u : side == 32 ? 5u : side == 64 ? 6u : 0u;
+}
+
+void set_camera_rows(mm::PointArgs& a, const float m[16]) {
+    const int rows[3] = {0, 1, 3};
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 4; ++c) a.m[4 * r + c] = m[4 * rows[r] + c];
 }
 
 void fill_point_args(mm_view v) {
@@ -112,17 +148,8 @@ void fill_point_args(mm_view v) {
     a.fheight = static_cast<float>(d.height);
     a.seed_lo = static_cast<uint32_t>(d.seed);
     a.seed_hi = static_cast<uint32_t>(d.seed >> 32);
-    a.step = 0;
     a.amp = d.amplitude;
-    const int rows[3] = {0, 1, 3};
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 4; ++c) a.m[4 * r + c] = d.view_proj[4 * rows[r] + c];
-    mm::ResolveArgs& r = v->rargs;
-    r.depth = v->depth;
-    r.colour = v->colour;
-    r.npix = static_cast<uint64_t>(d.width) * d.height;
-    r.seed_lo = a.seed_lo;
-    r.seed_hi = a.seed_hi;
+    set_camera_rows(a, d.view_proj);
 }
 
 hipKernelNodeParams node_params(const mm::Launch& l, void** args) {
@@ -130,49 +157,189 @@ hipKernelNodeParams node_params(const mm::Launch& l, void** args) {
     p.func = const_cast<void*>(l.func);
     p.gridDim = l.grid;
     p.blockDim = l.block;
-    p.sharedMemBytes = 0;
+    p.sharedMemBytes = l.shared;
     p.kernelParams = args;
     p.extra = nullptr;
     return p;
 }
 
-// Builds the frame graph of a view. With timed set, event-record nodes
-// bracket each kernel: ev0 -> point -> ev1 -> resolve -> ev2.
-mm_status build_graph(mm_view v, bool timed, hipGraph_t* g_out, hipGraphExec_t* e_out,
-                      hipGraphNode_t* point_out, hipGraphNode_t* ev_out) {
-    hipGraph_t g = nullptr;
-    MM_HIP(hipGraphCreate(&g, 0));
-    void* pargs[] = {&v->args};
-    void* rargs[] = {&v->rargs};
-    hipKernelNodeParams pp = node_params(v->point_l, pargs);
-    hipKernelNodeParams rp = node_params(v->resolve_l, rargs);
-    hipGraphNode_t pn = nullptr, rn = nullptr, e0 = nullptr, e1 = nullptr, e2 = nullptr;
+bool binned(mm_view v) { return v->tuning.splat == MM_SPLAT_BINNED; }
+
+// Argument block of frame-graph node k.
+void* node_arg(mm_view v, size_t k) {
+    if (binned(v)) return k == 0 ? static_cast<void*>(&v->bargs) : static_cast<void*>(&v->targs);
+    return k == 0 ? static_cast<void*>(&v->args) : static_cast<void*>(&v->rargs);
+}
+
+void destroy_graph(FrameGraph& fg) {
+    if (fg.exec) (void)hipGraphExecDestroy(fg.exec);
+    if (fg.graph) (void)hipGraphDestroy(fg.graph);
+    fg = FrameGraph{};
+}
+
+// The frame graph: the kernels of v->nodes in a chain; with timed set,
+// event-record nodes go before the first kernel, after it, and at the end.
+mm_status build_graph(mm_view v, bool timed, FrameGraph& out) {
+    FrameGraph fg;
+    MM_HIP(hipGraphCreate(&fg.graph, 0));
     hipError_t err = hipSuccess;
-    if (!timed) {
-        err = hipGraphAddKernelNode(&pn, g, nullptr, 0, &pp);
-        if (err == hipSuccess) err = hipGraphAddKernelNode(&rn, g, &pn, 1, &rp);
-    } else {
-        err = hipGraphAddEventRecordNode(&e0, g, nullptr, 0, v->events[0]);
-        if (err == hipSuccess) err = hipGraphAddKernelNode(&pn, g, &e0, 1, &pp);
-        if (err == hipSuccess) err = hipGraphAddEventRecordNode(&e1, g, &pn, 1, v->events[1]);
-        if (err == hipSuccess) err = hipGraphAddKernelNode(&rn, g, &e1, 1, &rp);
-        if (err == hipSuccess) err = hipGraphAddEventRecordNode(&e2, g, &rn, 1, v->events[2]);
+    hipGraphNode_t prev = nullptr;
+    auto add_event = [&](int j) {
+        if (err != hipSuccess) return;
+        err = hipGraphAddEventRecordNode(&fg.ev[j], fg.graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                         v->events[j]);
+        prev = fg.ev[j];
+    };
+    if (timed) add_event(0);
+    for (size_t k = 0; k < v->nodes.size() && err == hipSuccess; ++k) {
+        void* args[] = {node_arg(v, k)};
+        hipKernelNodeParams p = node_params(v->nodes[k], args);
+        hipGraphNode_t n = nullptr;
+        err = hipGraphAddKernelNode(&n, fg.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (k == 0) fg.first = n;
+        prev = n;
+        if (timed && k == 0) add_event(1);
     }
-    hipGraphExec_t e = nullptr;
-    if (err == hipSuccess) err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (timed) add_event(2);
+    if (err == hipSuccess) err = hipGraphInstantiate(&fg.exec, fg.graph, nullptr, nullptr, 0);
     if (err != hipSuccess) {
-        (void)hipGraphDestroy(g);
+        destroy_graph(fg);
         return fail(MM_ERR_HIP, "building the frame graph failed: %s", hipGetErrorString(err));
     }
-    *g_out = g;
-    *e_out = e;
-    *point_out = pn;
-    if (ev_out) {
-        ev_out[0] = e0;
-        ev_out[1] = e1;
-        ev_out[2] = e2;
-    }
+    out = fg;
     return MM_OK;
+}
+
+void free_splat_buffers(mm_view v) {
+    for (void* p : {static_cast<void*>(v->depth), static_cast<void*>(v->seg),
+                    static_cast<void*>(v->table), static_cast<void*>(v->active),
+                    static_cast<void*>(v->border), static_cast<void*>(v->apron)})
+        if (p) (void)hipFree(p);
+    v->depth = nullptr;
+    v->seg = nullptr;
+    v->table = nullptr;
+    v->active = nullptr;
+    v->border = nullptr;
+    v->apron = nullptr;
+}
+
+// Resolves AUTO and zero fields of a requested tuning for this view.
+mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning& out) {
+    out = req;
+    if (out.splat > MM_SPLAT_BINNED)
+        return fail(MM_ERR_INVALID_ARG, "tuning: splat %u unknown", out.splat);
+    auto tiles = [&](uint32_t side) {
+        return ((d.width + side - 1) / side) * ((d.height + side - 1) / side);
+    };
+    if (out.splat == MM_SPLAT_AUTO) {
+        out.splat = (tiles(64) <= 4096u) ? MM_SPLAT_BINNED : MM_SPLAT_DIRECT;
+    }
+    if (out.splat == MM_SPLAT_DIRECT) {
+        out.tile = 0;
+        out.points_per_thread = 0;
+        return MM_OK;
+    }
+    if (out.tile == 0) out.tile = tiles(32) <= 4096u ? 32u : 64u;
+    if (out.points_per_thread == 0) out.points_per_thread = 16;
+    if (!mm::binned_shape_ok(static_cast<int>(shift_of(out.tile)), static_cast<int>(out.points_per_thread)))
+        return fail(MM_ERR_INVALID_ARG, "tuning: tile %u / points_per_thread %u not in {16,32,64} x {4,8,16}",
+                    out.tile, out.points_per_thread);
+    if (tiles(out.tile) > 4096u)
+        return fail(MM_ERR_UNSUPPORTED, "tuning: %ux%u screen needs %u tiles of %u px (max 4096)",
+                    d.width, d.height, tiles(out.tile), out.tile);
+    return MM_OK;
+}
+
+template <typename T>
+hipError_t alloc_n(T** p, uint64_t n) {
+    return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+}
+
+// Allocates the splat scratch buffers of v->tuning, fills the kernel
+// argument blocks and builds the plain frame graph.
+mm_status setup_splat(mm_view v) {
+    mm_instance inst = v->inst;
+    const mm_view_desc& d = v->desc;
+    const uint64_t npix = static_cast<uint64_t>(d.width) * d.height;
+    const int dim = static_cast<int>(d.domain), foot = static_cast<int>(d.footprint);
+    const bool wrap = d.wrap != 0;
+    hipError_t e = hipSuccess;
+    v->nodes.clear();
+    if (!binned(v)) {
+        e = alloc_n(&v->depth, npix);
+        if (e == hipSuccess) e = mm::launch_fill(v->depth, npix, mm::kEmptyKey, inst->stream);
+        if (e != hipSuccess) return hip_fail(e, "direct splat buffers");
+        fill_point_args(v);
+        v->rargs = mm::ResolveArgs{v->depth, v->colour, npix, v->args.seed_lo, v->args.seed_hi};
+        v->nodes.push_back(mm::point_launch(dim, foot, wrap, mm::kDisplaceRender, v->args.n));
+        v->nodes.push_back(mm::resolve_launch(npix));
+    } else {
+        const uint32_t side = v->tuning.tile, shift = shift_of(side);
+        const int ppt = static_cast<int>(v->tuning.points_per_thread);
+        const uint64_t P = 256ull * static_cast<uint64_t>(ppt);
+        v->tiles_x = (d.width + side - 1) / side;
+        v->tiles_y = (d.height + side - 1) / side;
+        v->ntiles = v->tiles_x * v->tiles_y;
+        v->num_wg = static_cast<uint32_t>((d.element_count + P - 1) / P);
+        e = alloc_n(&v->seg, static_cast<uint64_t>(v->num_wg) * P);
+        if (e == hipSuccess) e = alloc_n(&v->table, static_cast<uint64_t>(v->num_wg) * (v->ntiles + 1));
+        if (e == hipSuccess) e = alloc_n(&v->active, static_cast<uint64_t>(v->ntiles) + 1);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(v->active, 0, (static_cast<size_t>(v->ntiles) + 1) * 4, inst->stream);
+        if (e == hipSuccess && foot == 3) {
+            e = alloc_n(&v->border, static_cast<uint64_t>(v->ntiles) * 4 * side);
+            if (e == hipSuccess) e = alloc_n(&v->apron, static_cast<uint64_t>(v->ntiles) * (4 * side + 4));
+        }
+        if (e != hipSuccess) return hip_fail(e, "binned splat buffers");
+        v->stamp = 0;
+        fill_point_args(v);
+        mm::BinArgs& b = v->bargs;
+        b.p = v->args;
+        b.seg = v->seg;
+        b.table = v->table;
+        b.active = v->active;
+        b.stamp_out = v->active + v->ntiles;
+        b.stamp = 0;
+        b.tiles_x = v->tiles_x;
+        b.ntiles = v->ntiles;
+        b.shift = shift;
+        mm::TileArgs& t = v->targs;
+        t.seg = v->seg;
+        t.table = v->table;
+        t.active = v->active;
+        t.stamp_in = v->active + v->ntiles;
+        t.border = v->border;
+        t.apron = v->apron;
+        t.colour = v->colour;
+        t.width = d.width;
+        t.height = d.height;
+        t.tiles_x = v->tiles_x;
+        t.tiles_y = v->tiles_y;
+        t.ntiles = v->ntiles;
+        t.num_wg = v->num_wg;
+        t.points_per_wg = static_cast<uint32_t>(P);
+        t.seed_lo = v->args.seed_lo;
+        t.seed_hi = v->args.seed_hi;
+        v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, v->args.n, v->ntiles));
+        v->nodes.push_back(mm::tile_launch(foot, static_cast<int>(shift), v->ntiles));
+        if (foot == 3) v->nodes.push_back(mm::seam_launch(static_cast<int>(shift), v->ntiles));
+    }
+    return build_graph(v, false, v->plain);
+}
+
+void teardown_splat(mm_view v) {
+    destroy_graph(v->plain);
+    destroy_graph(v->timed);
+    v->profiling = false;
+    free_splat_buffers(v);
+}
+
+void destroy_view_resources(mm_view v) {
+    teardown_splat(v);
+    for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
+    v->events.clear();
+    if (v->colour) (void)hipFree(v->colour);
+    v->colour = nullptr;
 }
 
 mm_status validate_desc(mm_instance inst, const mm_view_desc* d) {
@@ -201,7 +368,7 @@ mm_status validate_desc(mm_instance inst, const mm_view_desc* d) {
                     d->width, d->height);
     if (d->footprint != 1 && d->footprint != 3)
         return fail(MM_ERR_INVALID_ARG, "view: footprint %u is not 1 or 3", d->footprint);
-    if (!(d->amplitude == 0.0f || finite_positive_pow2_range(d->amplitude)))
+    if (!amplitude_ok(d->amplitude))
         return fail(MM_ERR_INVALID_ARG, "view: amplitude %g outside {0} U [2^-64, 2^64]",
                     (double)d->amplitude);
     if (d->wrap != 0 && d->wrap != 1)
@@ -215,22 +382,22 @@ mm_status validate_desc(mm_instance inst, const mm_view_desc* d) {
     return MM_OK;
 }
 
-void destroy_view_resources(mm_view v) {
-    if (v->exec) (void)hipGraphExecDestroy(v->exec);
-    if (v->graph) (void)hipGraphDestroy(v->graph);
-    if (v->texec) (void)hipGraphExecDestroy(v->texec);
-    if (v->tgraph) (void)hipGraphDestroy(v->tgraph);
-    for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
-    v->events.clear();
-    if (v->depth) (void)hipFree(v->depth);
-    if (v->colour) (void)hipFree(v->colour);
+// Next frame stamp of a binned view; on wrap-around the tile stamps restart.
+mm_status next_stamp(mm_view v) {
+    if (++v->stamp == 0) {
+        MM_HIP(hipMemsetAsync(v->active, 0, (static_cast<size_t>(v->ntiles) + 1) * 4,
+                              v->inst->stream));
+        v->stamp = 1;
+    }
+    v->bargs.stamp = v->stamp;
+    return MM_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-int32_t mm_version(void) { return 100; }
+int32_t mm_version(void) { return 200; }
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
@@ -316,6 +483,7 @@ mm_status mm_alloc_wrap(mm_instance inst, void* dev_ptr, size_t bytes, mm_alloc*
     if (bytes == 0) return fail(MM_ERR_INVALID_ARG, "alloc_wrap: zero bytes");
     if (reinterpret_cast<uintptr_t>(dev_ptr) % 4 != 0)
         return fail(MM_ERR_INVALID_ARG, "alloc_wrap: pointer not 4-byte aligned");
+    DeviceGuard guard(inst->device);
     hipPointerAttribute_t attr{};
     const hipError_t e = hipPointerGetAttributes(&attr, dev_ptr);
     if (e != hipSuccess || attr.type != hipMemoryTypeDevice || attr.device != inst->device) {
@@ -360,35 +528,24 @@ mm_status mm_create_view(mm_instance inst, const mm_view_desc* desc, mm_view* ou
     if (!inst || !desc || !out) return fail(MM_ERR_INVALID_ARG, "create_view: null argument");
     if (!desc->position || inst->allocs.count(desc->position) == 0)
         return fail(MM_ERR_INVALID_ARG, "create_view: position is not an alloc of this instance");
-    const mm_status vs = validate_desc(inst, desc);
-    if (vs != MM_OK) return vs;
+    MM_TRY(validate_desc(inst, desc));
+    mm_tuning tuning{};
+    MM_TRY(resolve_tuning(*desc, mm_tuning{MM_SPLAT_AUTO, 0, 0}, tuning));
     DeviceGuard guard(inst->device);
     mm_view v = new (std::nothrow) mm_view_s();
     if (!v) return fail(MM_ERR_OUT_OF_MEMORY, "create_view: host allocation");
     v->inst = inst;
     v->position = desc->position;
     v->desc = *desc;
+    v->tuning = tuning;
     const uint64_t npix = static_cast<uint64_t>(desc->width) * desc->height;
-    hipError_t e = hipMalloc(&v->depth, npix * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMalloc(&v->colour, npix * sizeof(uint32_t));
-    if (e == hipSuccess) e = mm::launch_fill(v->depth, npix, inst->stream);
+    hipError_t e = alloc_n(&v->colour, npix);
     if (e == hipSuccess) e = hipMemsetAsync(v->colour, 0, npix * sizeof(uint32_t), inst->stream);
-    if (e != hipSuccess) {
+    mm_status st = e == hipSuccess ? setup_splat(v) : hip_fail(e, "create_view: frame buffer");
+    if (st != MM_OK) {
         destroy_view_resources(v);
         delete v;
-        return fail(e == hipErrorOutOfMemory ? MM_ERR_OUT_OF_MEMORY : MM_ERR_HIP,
-                    "create_view: device buffers: %s", hipGetErrorString(e));
-    }
-    fill_point_args(v);
-    const int dim = static_cast<int>(desc->domain);
-    v->point_l = mm::point_launch(dim, static_cast<int>(desc->footprint), desc->wrap != 0,
-                                  mm::kDisplaceRender, v->args.n);
-    v->resolve_l = mm::resolve_launch(npix);
-    const mm_status gs = build_graph(v, false, &v->graph, &v->exec, &v->point_node, nullptr);
-    if (gs != MM_OK) {
-        destroy_view_resources(v);
-        delete v;
-        return gs;
+        return st;
     }
     desc->position->users++;
     inst->views.insert(v);
@@ -399,6 +556,7 @@ mm_status mm_create_view(mm_instance inst, const mm_view_desc* desc, mm_view* ou
 mm_status mm_destroy_view(mm_view v) {
     if (!v) return fail(MM_ERR_INVALID_ARG, "destroy_view: null view");
     mm_instance inst = v->inst;
+    if (!inst->views.count(v)) return fail(MM_ERR_INVALID_ARG, "destroy_view: unknown view");
     DeviceGuard guard(inst->device);
     MM_HIP(hipStreamSynchronize(inst->stream));
     destroy_view_resources(v);
@@ -408,54 +566,100 @@ mm_status mm_destroy_view(mm_view v) {
     return MM_OK;
 }
 
+mm_status mm_set_tuning(mm_view v, const mm_tuning* req) {
+    if (!v || !req) return fail(MM_ERR_INVALID_ARG, "set_tuning: null argument");
+    mm_tuning t{};
+    MM_TRY(resolve_tuning(v->desc, *req, t));
+    DeviceGuard guard(v->inst->device);
+    MM_HIP(hipStreamSynchronize(v->inst->stream));
+    teardown_splat(v);
+    v->tuning = t;
+    const mm_status st = setup_splat(v);
+    if (st != MM_OK) teardown_splat(v);  // the view is unusable until a tuning succeeds
+    return st;
+}
+
+mm_status mm_get_tuning(mm_view v, mm_tuning* out) {
+    if (!v || !out) return fail(MM_ERR_INVALID_ARG, "get_tuning: null argument");
+    *out = v->tuning;
+    return MM_OK;
+}
+
 mm_status mm_set_camera(mm_view v, const float m[16]) {
     if (!v || !m) return fail(MM_ERR_INVALID_ARG, "set_camera: null argument");
     for (int k = 0; k < 16; ++k)
         if (!std::isfinite(m[k])) return fail(MM_ERR_INVALID_ARG, "set_camera: m[%d] not finite", k);
     std::memcpy(v->desc.view_proj, m, sizeof(float) * 16);
-    const int rows[3] = {0, 1, 3};
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 4; ++c) v->args.m[4 * r + c] = m[4 * rows[r] + c];
+    set_camera_rows(v->args, m);
+    set_camera_rows(v->bargs.p, m);
+    return MM_OK;
+}
+
+static mm_status require_ready(mm_view v, const char* what) {
+    if (!v) return fail(MM_ERR_INVALID_ARG, "%s: null view", what);
+    if (!v->plain.exec) return fail(MM_ERR_INVALID_ARG, "%s: view has no usable tuning", what);
     return MM_OK;
 }
 
 mm_status mm_step(mm_view v, uint32_t step) {
-    if (!v) return fail(MM_ERR_INVALID_ARG, "step: null view");
+    MM_TRY(require_ready(v, "step"));
     DeviceGuard guard(v->inst->device);
-    v->args.step = step;
-    MM_HIP(mm::launch_point(v->args, static_cast<int>(v->desc.domain),
-                            static_cast<int>(v->desc.footprint), v->desc.wrap != 0,
-                            mm::kDisplace, v->inst->stream));
+    mm::PointArgs a = v->args;
+    a.step = step;
+    MM_HIP(mm::launch_point(a, static_cast<int>(v->desc.domain), static_cast<int>(v->desc.footprint),
+                            v->desc.wrap != 0, mm::kDisplace, v->inst->stream));
     return MM_OK;
 }
 
 mm_status mm_render(mm_view v) {
-    if (!v) return fail(MM_ERR_INVALID_ARG, "render: null view");
+    MM_TRY(require_ready(v, "render"));
     DeviceGuard guard(v->inst->device);
-    MM_HIP(mm::launch_point(v->args, static_cast<int>(v->desc.domain),
-                            static_cast<int>(v->desc.footprint), v->desc.wrap != 0,
-                            mm::kRender, v->inst->stream));
-    MM_HIP(mm::launch_resolve(v->rargs, v->inst->stream));
+    hipStream_t s = v->inst->stream;
+    const int dim = static_cast<int>(v->desc.domain), foot = static_cast<int>(v->desc.footprint);
+    if (!binned(v)) {
+        MM_HIP(mm::launch_point(v->args, dim, foot, v->desc.wrap != 0, mm::kRender, s));
+        MM_HIP(mm::launch_resolve(v->rargs, s));
+        return MM_OK;
+    }
+    MM_TRY(next_stamp(v));
+    const mm::Launch b = mm::bin_launch(dim, v->desc.wrap != 0, mm::kRender,
+                                        static_cast<int>(v->tuning.points_per_thread), v->args.n,
+                                        v->ntiles);
+    void* bargs[] = {&v->bargs};
+    MM_HIP(hipLaunchKernel(b.func, b.grid, b.block, bargs, b.shared, s));
+    for (size_t k = 1; k < v->nodes.size(); ++k) {
+        void* targs[] = {&v->targs};
+        MM_HIP(hipLaunchKernel(v->nodes[k].func, v->nodes[k].grid, v->nodes[k].block, targs,
+                               v->nodes[k].shared, s));
+    }
     return MM_OK;
 }
 
 mm_status mm_step_render(mm_view v, uint32_t step) {
-    if (!v) return fail(MM_ERR_INVALID_ARG, "step_render: null view");
+    MM_TRY(require_ready(v, "step_render"));
     DeviceGuard guard(v->inst->device);
-    v->args.step = step;
-    void* pargs[] = {&v->args};
-    hipKernelNodeParams pp = node_params(v->point_l, pargs);
+    void* first_arg;
+    if (binned(v)) {
+        MM_TRY(next_stamp(v));
+        v->bargs.p.step = step;
+        first_arg = &v->bargs;
+    } else {
+        v->args.step = step;
+        first_arg = &v->args;
+    }
+    void* args[] = {first_arg};
+    hipKernelNodeParams pp = node_params(v->nodes[0], args);
     if (v->profiling && v->prof_count < v->prof_cap) {
         const uint32_t k = v->prof_count++;
         for (int j = 0; j < 3; ++j)
-            MM_HIP(hipGraphExecEventRecordNodeSetEvent(v->texec, v->tevent_node[j],
-                                                       v->events[3 * k + j]));
-        MM_HIP(hipGraphExecKernelNodeSetParams(v->texec, v->tpoint_node, &pp));
-        MM_HIP(hipGraphLaunch(v->texec, v->inst->stream));
+            MM_HIP(hipGraphExecEventRecordNodeSetEvent(v->timed.exec, v->timed.ev[j],
+                                                       v->events[3ull * k + j]));
+        MM_HIP(hipGraphExecKernelNodeSetParams(v->timed.exec, v->timed.first, &pp));
+        MM_HIP(hipGraphLaunch(v->timed.exec, v->inst->stream));
         return MM_OK;
     }
-    MM_HIP(hipGraphExecKernelNodeSetParams(v->exec, v->point_node, &pp));
-    MM_HIP(hipGraphLaunch(v->exec, v->inst->stream));
+    MM_HIP(hipGraphExecKernelNodeSetParams(v->plain.exec, v->plain.first, &pp));
+    MM_HIP(hipGraphLaunch(v->plain.exec, v->inst->stream));
     return MM_OK;
 }
 
@@ -476,19 +680,16 @@ mm_status mm_read_frame(mm_view v, void* host_rgba, size_t bytes) {
 }
 
 mm_status mm_profile_begin(mm_view v, uint32_t capacity) {
-    if (!v || capacity == 0 || capacity > (1u << 20))
-        return fail(MM_ERR_INVALID_ARG, "profile_begin: null view or capacity outside [1, 2^20]");
+    MM_TRY(require_ready(v, "profile_begin"));
+    if (capacity == 0 || capacity > (1u << 20))
+        return fail(MM_ERR_INVALID_ARG, "profile_begin: capacity outside [1, 2^20]");
     DeviceGuard guard(v->inst->device);
     MM_HIP(hipStreamSynchronize(v->inst->stream));
-    if (v->texec) (void)hipGraphExecDestroy(v->texec);
-    if (v->tgraph) (void)hipGraphDestroy(v->tgraph);
-    v->texec = nullptr;
-    v->tgraph = nullptr;
+    destroy_graph(v->timed);
     for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
     v->events.assign(3ull * capacity, nullptr);
     for (auto& e : v->events) MM_HIP(hipEventCreate(&e));
-    const mm_status gs = build_graph(v, true, &v->tgraph, &v->texec, &v->tpoint_node, v->tevent_node);
-    if (gs != MM_OK) return gs;
+    MM_TRY(build_graph(v, true, v->timed));
     v->prof_cap = capacity;
     v->prof_count = 0;
     v->profiling = true;

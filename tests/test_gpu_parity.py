@@ -27,12 +27,28 @@ def rig(torch_gpu):
     r.close()
 
 
+# splat strategies and shapes: (splat, tile, points_per_thread); 0 = auto
+DIRECT = (1, 0, 0)
+BINNED = (2, 0, 0)
+MODES = [DIRECT, BINNED]
+SHAPES = [DIRECT, (2, 16, 4), (2, 32, 8), (2, 64, 16)]
+
+
+def _ids(modes):
+    return ["direct" if m[0] == 1 else f"binned-t{m[1]}-p{m[2]}" for m in modes]
+
+
 def _run(rig, pts, dim, w, h, foot, seed, amp, wrap, frames, cam_fn, check_every=1,
-         split=False):
+         split=False, mode=None):
     mm = rig.mm
     n = pts.shape[0]
     dev, alloc = rig.cloud(pts)
     view = rig.view(alloc, n, dim, w, h, foot, seed, amp, wrap, cam_fn(0))
+    if mode is not None:
+        mm.mm_set_tuning(view, *mode)
+        got_mode = mm.mm_get_tuning(view)
+        assert got_mode[0] == mode[0]
+        say(f"  tuning {got_mode}")
     ref = pts.copy()
     for s in range(frames):
         cam = cam_fn(s)
@@ -53,89 +69,105 @@ def _run(rig, pts, dim, w, h, foot, seed, amp, wrap, frames, cam_fn, check_every
     return ref
 
 
-def test_2d_65536_points_512sq_100_steps(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_2d_65536_points_512sq_100_steps(rig, mode):
     say("case: 2D uniform, 65536 points, 512x512, a=0.005, wrap, 100 steps, every step")
     pts = synth.uniform_square(65536, seed=0)
-    _run(rig, pts, 2, 512, 512, 1, 0, 0.005, True, 100, lambda s: synth.IDENTITY)
+    _run(rig, pts, 2, 512, 512, 1, 0, 0.005, True, 100, lambda s: synth.IDENTITY, mode=mode)
 
 
-def test_3d_uniform_ragged_small(rig):
+@pytest.mark.parametrize("mode", SHAPES, ids=_ids(SHAPES))
+def test_3d_uniform_ragged_small(rig, mode):
     say("case: 3D uniform, 65613 points (ragged), 320x240, 12 frames")
     pts = synth.uniform_cube(65536 + 77, seed=3)
     _run(rig, pts, 3, 320, 240, 1, 3, 0.001, False, 12,
-         lambda s: synth.orbit_camera(s, 320, 240))
+         lambda s: synth.orbit_camera(s, 320, 240), mode=mode)
 
 
-def test_3d_split_step_render_matches(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_3d_split_step_render_matches(rig, mode):
     say("case: 3D uniform, mm_step + mm_render, 30001 points, 200x100, 5 frames")
     pts = synth.uniform_cube(30001, seed=4)
     _run(rig, pts, 3, 200, 100, 1, 4, 0.001, False, 5,
-         lambda s: synth.orbit_camera(3 * s, 200, 100), split=True)
+         lambda s: synth.orbit_camera(3 * s, 200, 100), split=True, mode=mode)
 
 
-def test_3d_footprint3_mixture(rig):
+@pytest.mark.parametrize("mode", SHAPES, ids=_ids(SHAPES))
+def test_3d_footprint3_mixture(rig, mode):
     say("case: 3D mixture sigma 0.02, 3x3 footprint, 2^18 points, 640x360, 4 frames")
     pts = synth.gaussian_mixture(1 << 18, seed=0)
     _run(rig, pts, 3, 640, 360, 3, 0, 0.001, False, 4,
-         lambda s: synth.orbit_camera(s, 640, 360))
+         lambda s: synth.orbit_camera(s, 640, 360), mode=mode)
 
 
-def test_2d_footprint3_ties(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_2d_footprint3_ties(rig, mode):
     say("case: 2D grid points with heavy ties, 3x3 footprint, 20000 points, 64x64")
     rng = np.random.default_rng(0)
     pts = (rng.integers(-32, 32, size=(20000, 2)) / 32.0).astype(np.float32)
-    _run(rig, pts, 2, 64, 64, 3, 9, 0.0, False, 2, lambda s: synth.IDENTITY)
+    _run(rig, pts, 2, 64, 64, 3, 9, 0.0, False, 2, lambda s: synth.IDENTITY, mode=mode)
 
 
-def test_3d_2p20_points_1080p(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_3d_2p20_points_1080p(rig, mode):
     say("case: 3D uniform, 2^20 points, 1920x1080, 3 frames")
     pts = synth.uniform_cube(1 << 20, seed=0)
     _run(rig, pts, 3, 1920, 1080, 1, 0, 0.001, False, 3,
-         lambda s: synth.orbit_camera(s, 1920, 1080))
+         lambda s: synth.orbit_camera(s, 1920, 1080), mode=mode)
 
 
-def test_3d_2p24_points_1080p_full_size(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_3d_2p24_points_1080p_full_size(rig, mode):
     say("case: 3D uniform, 2^24 points, 1920x1080, 2 frames (full benchmark size)")
     pts = synth.uniform_cube(1 << 24, seed=0)
     _run(rig, pts, 3, 1920, 1080, 1, 0, 0.001, False, 2,
-         lambda s: synth.orbit_camera(s, 1920, 1080))
+         lambda s: synth.orbit_camera(s, 1920, 1080), mode=mode)
 
 
-def test_3d_mixture_4k_footprint3(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_3d_mixture_4k_footprint3(rig, mode):
     say("case: 3D mixture, 2^22 points, 3840x2160, 3x3 footprint, 2 frames")
     pts = synth.gaussian_mixture(1 << 22, seed=0)
     _run(rig, pts, 3, 3840, 2160, 3, 0, 0.001, False, 2,
-         lambda s: synth.orbit_camera(s, 3840, 2160))
+         lambda s: synth.orbit_camera(s, 3840, 2160), mode=mode)
 
 
-@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 1025])
-def test_tiny_and_ragged_counts(rig, n):
-    say(f"case: 3D uniform, {n} points, 16x8 and 2D {n} points 8x8")
+@pytest.mark.parametrize("mode", SHAPES, ids=_ids(SHAPES))
+@pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 1025, 4097])
+def test_tiny_and_ragged_counts(rig, n, mode):
+    say(f"case: 3D uniform, {n} points, 16x8 and 2D {n} points 8x8, mode {mode}")
     _run(rig, synth.uniform_cube(n, seed=n), 3, 16, 8, 3, n, 0.001, False, 3,
-         lambda s: synth.orbit_camera(10 * s, 16, 8))
+         lambda s: synth.orbit_camera(10 * s, 16, 8), mode=mode)
     _run(rig, synth.uniform_square(n, seed=n), 2, 8, 8, 1, n, 0.005, True, 3,
-         lambda s: synth.IDENTITY)
+         lambda s: synth.IDENTITY, mode=mode)
+    # a screen that is not a whole number of tiles
+    _run(rig, synth.uniform_cube(n, seed=n + 1), 3, 70, 38, 3, n, 0.001, False, 2,
+         lambda s: synth.orbit_camera(20 * s, 70, 38), mode=mode)
 
 
-def test_smallest_screen_and_everything_culled(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_smallest_screen_and_everything_culled(rig, mode):
     say("case: 2x2 screen; camera looking away (all culled)")
     pts = synth.uniform_cube(4096, seed=1)
-    _run(rig, pts, 3, 2, 2, 3, 1, 0.001, False, 2, lambda s: synth.orbit_camera(s, 2, 2))
+    _run(rig, pts, 3, 2, 2, 3, 1, 0.001, False, 2, lambda s: synth.orbit_camera(s, 2, 2),
+         mode=mode)
     away = synth.look_at_perspective((0.5, 0.5, 3.0), (0.5, 0.5, 6.0), (0, 1, 0), 60.0, 1.0)
     mm = rig.mm
     dev, alloc = rig.cloud(pts)
     view = rig.view(alloc, 4096, 3, 32, 32, 1, 1, 0.001, False, away)
+    mm.mm_set_tuning(view, *mode)
     mm.mm_step_render(view, 0)
     assert not mm.mm_read_frame(view, 32, 32).any()
 
 
-def test_2d_points_on_pixel_edges_and_borders(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_2d_points_on_pixel_edges_and_borders(rig, mode):
     say("case: 2D points on pixel edges, corners and just inside/outside the box")
     w, h = 64, 32
     xs = np.array([-1.0, 1.0 - 2.0**-23, 1.0 - 2.0**-24, 0.0, -0.5, 2.0 / 64 - 1.0],
                   dtype=np.float32)
     pts = np.array([[x, y] for x in xs for y in xs], dtype=np.float32)
-    _run(rig, pts, 2, w, h, 3, 5, 0.0, False, 1, lambda s: synth.IDENTITY)
+    _run(rig, pts, 2, w, h, 3, 5, 0.0, False, 1, lambda s: synth.IDENTITY, mode=mode)
 
 
 def test_view_sharing_one_cloud(rig):
@@ -146,6 +178,8 @@ def test_view_sharing_one_cloud(rig):
     va = rig.view(alloc, 50000, 3, 160, 120, 1, 2, 0.001, False, synth.orbit_camera(0, 160, 120))
     camb = synth.orbit_camera(90, 256, 256)
     vb = rig.view(alloc, 50000, 3, 256, 256, 3, 2, 0.001, False, camb)
+    mm.mm_set_tuning(va, *BINNED)
+    mm.mm_set_tuning(vb, *DIRECT)
     ref = pts.copy()
     for s in range(3):
         mm.mm_step_render(va, s)
@@ -203,13 +237,15 @@ def test_resume_from_snapshot(rig):
     assert same_bits(rig.positions(dev), rig.positions(dev2))
 
 
-def test_profile_records_kernel_times(rig):
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_profile_records_kernel_times(rig, mode):
     say("case: mm_profile_begin/end around 20 frames, 2^20 points 1080p")
     mm = rig.mm
     pts = synth.uniform_cube(1 << 20, seed=0)
     dev, alloc = rig.cloud(pts)
     view = rig.view(alloc, 1 << 20, 3, 1920, 1080, 1, 0, 0.001, False,
                     synth.orbit_camera(0, 1920, 1080))
+    mm.mm_set_tuning(view, *mode)
     mm.mm_profile_begin(view, 20)
     ref = pts.copy()
     for s in range(25):  # 5 beyond capacity run untimed
@@ -273,3 +309,47 @@ def test_invalid_descriptions_are_rejected(rig):
         mm.mm_set_camera(view, bad)
     with pytest.raises(mm.MMError):
         mm.mm_read_frame(view, 32, 32)  # too small a host buffer
+
+
+def test_tuning_choices_and_validation(rig):
+    say("case: tuning resolution and rejection")
+    mm = rig.mm
+    pts = synth.uniform_cube(5000, seed=0)
+    dev, alloc = rig.cloud(pts)
+    cam = synth.orbit_camera(0, 1920, 1080)
+    view = rig.view(alloc, 5000, 3, 1920, 1080, 1, 0, 0.001, False, cam)
+    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 16)
+    for bad, status in [((2, 128, 16), mm.MM_ERR_INVALID_ARG), ((2, 32, 3), mm.MM_ERR_INVALID_ARG),
+                        ((7, 0, 0), mm.MM_ERR_INVALID_ARG), ((2, 16, 16), mm.MM_ERR_UNSUPPORTED)]:
+        with pytest.raises(mm.MMError) as e:
+            mm.mm_set_tuning(view, *bad)
+        assert e.value.status == status, (bad, str(e.value))
+    # a rejected tuning leaves the previous one working
+    mm.mm_step_render(view, 0)
+    ref = pts.copy()
+    assert np.array_equal(mm.mm_read_frame(view, 1920, 1080),
+                          oracle.step_render(ref, 0, 0, 0.001, False, cam, 1920, 1080, 1))
+    mm.mm_set_tuning(view, 2, 64, 4)
+    assert mm.mm_get_tuning(view) == (2, 64, 4)
+    mm.mm_step_render(view, 1)
+    assert np.array_equal(mm.mm_read_frame(view, 1920, 1080),
+                          oracle.step_render(ref, 0, 1, 0.001, False, cam, 1920, 1080, 1))
+    mm.mm_set_tuning(view, 1, 0, 0)
+    assert mm.mm_get_tuning(view) == (1, 0, 0)
+
+
+def test_largest_screen_falls_back_to_direct(rig):
+    say("case: 16384x16384 screen, 3x3 footprint, 6000 points (direct only)")
+    mm = rig.mm
+    n, w = 6000, 16384
+    pts = synth.gaussian_mixture(n, seed=5, sigma=0.2)
+    dev, alloc = rig.cloud(pts)
+    cam = synth.orbit_camera(30, w, w)
+    view = rig.view(alloc, n, 3, w, w, 3, 5, 0.001, False, cam)
+    assert mm.mm_get_tuning(view)[0] == mm.MM_SPLAT_DIRECT
+    mm.mm_step_render(view, 0)
+    got = mm.mm_read_frame(view, w, w)
+    ref = pts.copy()
+    want = oracle.step_render(ref, 5, 0, 0.001, False, cam, w, w, 3)
+    assert np.array_equal(got, want)
+    mm.mm_destroy_view(view)
