@@ -28,30 +28,54 @@ using namespace dev;
 
 constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
 
-// Exclusive scan of h[0..count) in place by 256 threads; h[count] = total.
-__device__ void block_exclusive_scan(uint32_t* h, uint32_t count, uint32_t* wave_sum) {
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    const uint32_t per = (count + 255u) / 256u;
-    const uint32_t lo = min(count, tid * per), hi = min(count, lo + per);
-    uint32_t s = 0;
-    for (uint32_t b = lo; b < hi; ++b) s += h[b];
-    uint32_t v = s;
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, uint32_t lane) {
 #pragma unroll
     for (uint32_t d = 1; d < 64; d <<= 1) {
         const uint32_t u = __shfl_up(v, d, 64);
         if (lane >= d) v += u;
     }
-    if (lane == 63u) wave_sum[wave] = v;
-    __syncthreads();
-    uint32_t off = 0;
-    for (uint32_t w = 0; w < wave; ++w) off += wave_sum[w];
-    uint32_t run = off + v - s;
-    for (uint32_t b = lo; b < hi; ++b) {
-        const uint32_t c = h[b];
-        h[b] = run;
-        run += c;
+    return v;
+}
+
+// Per-tile frame stamps: relaxed atomics at wavefront scope, which compile to
+// plain cached loads and stores.
+__device__ __forceinline__ void store_flag(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ uint32_t load_flag(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// Exclusive scan of h[0..count) in place by 256 threads; h[count] = total.
+// Each wave owns a contiguous run of 64-bin blocks and reads every block with
+// consecutive lanes on consecutive words, so LDS accesses never conflict.
+__device__ void block_exclusive_scan(uint32_t* h, uint32_t count, uint32_t* wave_sum) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t nblk = (count + 63u) / 64u;
+    const uint32_t per = (nblk + 3u) / 4u;
+    const uint32_t b0 = min(nblk, wave * per), b1 = min(nblk, b0 + per);
+    uint32_t lsum = 0;
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t i = b * 64u + lane;
+        lsum += i < count ? h[i] : 0u;
     }
-    if (tid == 255u) h[count] = off + v;
+    const uint32_t wtot = __shfl(wave_inclusive_scan(lsum, lane), 63, 64);
+    if (lane == 0) wave_sum[wave] = wtot;
+    __syncthreads();
+    uint32_t carry = 0, total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < 4; ++w) {
+        carry += w < wave ? wave_sum[w] : 0u;
+        total += wave_sum[w];
+    }
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t i = b * 64u + lane;
+        const uint32_t v = i < count ? h[i] : 0u;
+        const uint32_t inc = wave_inclusive_scan(v, lane);
+        if (i < count) h[i] = carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+    }
+    if (tid == 0) h[count] = total;
 }
 
 template <int DIM, bool WRAP, int PHASE, int PPT>
@@ -129,14 +153,13 @@ __global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
     uint16_t* row = a.table + static_cast<uint64_t>(blockIdx.x) * (nt + 1u);
     for (uint32_t b = tid; b <= nt; b += 256u)
         row[b] = static_cast<uint16_t>(b == 0 ? 0u : hist[b - 1]);
-    // Stamp the tiles that received points. Every workgroup reaches much the
-    // same tiles, so check first (a cached load: a stale value only costs a
-    // redundant store) and store only where this frame's stamp is missing.
+    // Stamp the tiles that received points. All workgroups write the same
+    // value, so the stores are plain cached ones (relaxed atomics at
+    // wavefront scope carry no cache-bypass bits); the kernel boundary makes
+    // them visible to the tile pass.
     for (uint32_t b = tid; b < nt; b += 256u) {
         const uint32_t s = b == 0 ? 0u : hist[b - 1];
-        if (hist[b] > s &&
-            __hip_atomic_load(&a.active[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != a.stamp)
-            __hip_atomic_store(&a.active[b], a.stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (hist[b] > s) store_flag(&a.active[b], a.stamp);
     }
 }
 
@@ -174,8 +197,10 @@ __device__ __forceinline__ uint32_t ring_index(uint32_t ax, uint32_t ay) {
     return 3 * S + 4 + ay - 1;
 }
 
-__device__ __forceinline__ bool tile_active(const TileArgs& a, uint32_t t, uint32_t stamp) {
-    return __hip_atomic_load(&a.active[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == stamp;
+// The frame stamp is never 0 and rises by one per render; a tile's flag
+// equal to stamp - 1 means the tile was drawn in the previous frame.
+__device__ __forceinline__ uint32_t tile_flag(const TileArgs& a, uint32_t t) {
+    return load_flag(&a.active[t]);
 }
 
 template <int FOOT, uint32_t S, uint32_t A>
@@ -200,7 +225,7 @@ __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
     constexpr uint32_t kCol = 4096;    // bin workgroups per pass over the column
     constexpr uint32_t kGroup = S;     // lanes reading one chunk
     constexpr uint32_t kGroups = 1024u / kGroup;
-    constexpr uint32_t kInFlight = 8;  // chunks per lane group per round
+    constexpr uint32_t kInFlight = 16; // chunks per lane group per round
     constexpr uint32_t kPieces = 2;    // records per lane per chunk per round
     __shared__ uint64_t keys[A * A];
     __shared__ uint32_t col[kCol];     // start << 16 | count, per bin workgroup
@@ -212,10 +237,15 @@ __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
     const uint32_t wt = min(S, a.width - x0), ht = min(S, a.height - y0);
     uint32_t* out = a.colour + static_cast<uint64_t>(y0) * a.width + x0;
 
-    if (!tile_active(a, t, *a.stamp_in)) {
-        for (uint32_t q = tid; q < S * S; q += 1024u) {
-            const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
-            if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * a.width + lx] = 0u;
+    // Inactive tile: clear it if the previous frame drew it, else its pixels
+    // are already 0.
+    const uint32_t stamp = *a.stamp_in, flag = tile_flag(a, t);
+    if (flag != stamp) {
+        if (flag == stamp - 1u) {
+            for (uint32_t q = tid; q < S * S; q += 1024u) {
+                const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
+                if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * a.width + lx] = 0u;
+            }
         }
         return;
     }
@@ -227,46 +257,60 @@ __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
     for (uint32_t base = 0; base < a.num_wg; base += kCol) {
         const uint32_t nb = min(kCol, a.num_wg - base);
         __syncthreads();  // keys initialised / previous pass done with col
-        for (uint32_t c = tid; c < nb; c += 1024u) {
-            const uint16_t* row = a.table + static_cast<uint64_t>(base + c) * stride;
-            const uint32_t s = row[t], e = row[t + 1];
-            col[c] = (s << 16) | (e - s);
+        uint32_t cs[kCol / 1024], ce[kCol / 1024];
+#pragma unroll
+        for (uint32_t k = 0; k < kCol / 1024; ++k) {
+            const uint32_t c = tid + k * 1024u;
+            cs[k] = 0;
+            ce[k] = 0;
+            if (c < nb) {
+                const uint16_t* row = a.table + static_cast<uint64_t>(base + c) * stride;
+                cs[k] = row[t];
+                ce[k] = row[t + 1];
+            }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kCol / 1024; ++k) {
+            const uint32_t c = tid + k * 1024u;
+            if (c < nb) col[c] = (cs[k] << 16) | (ce[k] - cs[k]);
         }
         __syncthreads();
         for (uint32_t c0 = group; c0 < nb; c0 += kGroups * kInFlight) {
             uint64_t r[kInFlight][kPieces];
-            uint32_t cnt[kInFlight], first[kInFlight], gbase[kInFlight];
+            uint32_t v[kInFlight];  // start << 16 | count of chunk c0 + u * kGroups
 #pragma unroll
             for (uint32_t u = 0; u < kInFlight; ++u) {
                 const uint32_t c = c0 + u * kGroups;
-                const uint32_t v = c < nb ? col[c] : 0u;
-                cnt[u] = v & 0xFFFFu;
-                first[u] = v >> 16;
-                gbase[u] = (base + c) * P;
-                const uint64_t* src = a.seg + static_cast<uint64_t>(gbase[u]) + first[u];
+                v[u] = c < nb ? col[c] : 0u;
+                const uint64_t* src = a.seg + static_cast<uint64_t>(base + c) * P + (v[u] >> 16);
 #pragma unroll
                 for (uint32_t p = 0; p < kPieces; ++p) {
                     const uint32_t j = sub + p * kGroup;
-                    r[u][p] = j < cnt[u] ? src[j] : 0ull;
+                    r[u][p] = j < (v[u] & 0xFFFFu) ? src[j] : 0ull;
                 }
             }
 #pragma unroll
-            for (uint32_t u = 0; u < kInFlight; ++u)
+            for (uint32_t u = 0; u < kInFlight; ++u) {
+                const uint32_t gbase = (base + c0 + u * kGroups) * P;
 #pragma unroll
                 for (uint32_t p = 0; p < kPieces; ++p)
-                    if (sub + p * kGroup < cnt[u]) splat_record<FOOT, S, A>(keys, r[u][p], gbase[u]);
+                    if (sub + p * kGroup < (v[u] & 0xFFFFu))
+                        splat_record<FOOT, S, A>(keys, r[u][p], gbase);
+            }
             // the rest of chunks longer than kPieces * kGroup records
 #pragma unroll 1
             for (uint32_t u = 0; u < kInFlight; ++u) {
-                const uint64_t* src = a.seg + static_cast<uint64_t>(gbase[u]) + first[u];
-                for (uint32_t j = kPieces * kGroup + sub; j < cnt[u]; j += 4 * kGroup) {
+                const uint32_t cnt = v[u] & 0xFFFFu;
+                if (cnt <= kPieces * kGroup) continue;
+                const uint32_t gbase = (base + c0 + u * kGroups) * P;
+                const uint64_t* src = a.seg + static_cast<uint64_t>(gbase) + (v[u] >> 16);
+                for (uint32_t j = kPieces * kGroup + sub; j < cnt; j += 4 * kGroup) {
                     uint64_t rr[4];
 #pragma unroll
-                    for (uint32_t q = 0; q < 4; ++q)
-                        rr[q] = j + q * kGroup < cnt[u] ? src[j + q * kGroup] : 0ull;
+                    for (uint32_t q = 0; q < 4; ++q) rr[q] = j + q * kGroup < cnt ? src[j + q * kGroup] : 0ull;
 #pragma unroll
                     for (uint32_t q = 0; q < 4; ++q)
-                        if (j + q * kGroup < cnt[u]) splat_record<FOOT, S, A>(keys, rr[q], gbase[u]);
+                        if (j + q * kGroup < cnt) splat_record<FOOT, S, A>(keys, rr[q], gbase);
                 }
             }
         }
@@ -312,9 +356,12 @@ __global__ __launch_bounds__(256) void seam_kernel(TileArgs a) {
     const int32_t tx = static_cast<int32_t>(t % a.tiles_x), ty = static_cast<int32_t>(t / a.tiles_x);
     const uint32_t x0 = static_cast<uint32_t>(tx) << SHIFT, y0 = static_cast<uint32_t>(ty) << SHIFT;
     const uint32_t wt = min(S, a.width - x0), ht = min(S, a.height - y0);
-    const bool own = tile_active(a, t, stamp);
+    const uint32_t own_flag = tile_flag(a, t);
+    const bool own = own_flag == stamp;
+    // edges need work if this tile or a neighbour is drawn now, or was drawn
+    // in the previous frame (its edge pixels may hold last frame's colours)
     bool nb_active[9];
-    bool any = own;
+    bool any = own || own_flag == stamp - 1u;
 #pragma unroll
     for (int oy = -1; oy <= 1; ++oy)
 #pragma unroll
@@ -322,10 +369,12 @@ __global__ __launch_bounds__(256) void seam_kernel(TileArgs a) {
             const int nx = tx + ox, ny = ty + oy;
             bool act = false;
             if ((ox != 0 || oy != 0) && nx >= 0 && ny >= 0 && nx < static_cast<int32_t>(a.tiles_x) &&
-                ny < static_cast<int32_t>(a.tiles_y))
-                act = tile_active(a, static_cast<uint32_t>(ny) * a.tiles_x + nx, stamp);
+                ny < static_cast<int32_t>(a.tiles_y)) {
+                const uint32_t f = tile_flag(a, static_cast<uint32_t>(ny) * a.tiles_x + nx);
+                act = f == stamp;
+                any = any || act || f == stamp - 1u;
+            }
             nb_active[(oy + 1) * 3 + ox + 1] = act;
-            any = any || act;
         }
     if (!any) return;
     uint32_t* out = a.colour + static_cast<uint64_t>(y0) * a.width + x0;

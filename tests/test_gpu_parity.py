@@ -353,3 +353,30 @@ def test_largest_screen_falls_back_to_direct(rig):
     want = oracle.step_render(ref, 5, 0, 0.001, False, cam, w, w, 3)
     assert np.array_equal(got, want)
     mm.mm_destroy_view(view)
+
+
+@pytest.mark.parametrize("foot", [1, 3])
+@pytest.mark.parametrize("mode", SHAPES, ids=_ids(SHAPES))
+def test_frames_whose_tile_sets_change(rig, mode, foot):
+    say(f"case: consecutive frames drawing different tiles, footprint {foot}, mode {mode}")
+    mm = rig.mm
+    w, h = 640, 360
+    pts = synth.gaussian_mixture(60000, seed=11, sigma=0.03)
+    dev, alloc = rig.cloud(pts)
+    away = synth.look_at_perspective((0.5, 0.5, 3.0), (0.5, 0.5, 6.0), (0, 1, 0), 60.0, w / h)
+    zoom = synth.look_at_perspective((0.5, 0.5, 1.2), (0.5, 0.5, 0.5), (0, 1, 0), 60.0, w / h)
+    cams = [synth.orbit_camera(0, w, h), away, synth.orbit_camera(90, w, h),
+            synth.orbit_camera(90, w, h), zoom, away, away, synth.orbit_camera(200, w, h)]
+    view = rig.view(alloc, 60000, 3, w, h, foot, 11, 0.001, False, cams[0])
+    mm.mm_set_tuning(view, *mode)
+    ref = pts.copy()
+    for s, cam in enumerate(cams):
+        mm.mm_set_camera(view, cam)
+        if s % 3 == 2:
+            mm.mm_render(view)
+            want = oracle.render(ref, 11, cam, w, h, foot)
+        else:
+            mm.mm_step_render(view, s)
+            want = oracle.step_render(ref, 11, s, 0.001, False, cam, w, h, foot)
+        got = mm.mm_read_frame(view, w, h)
+        assert np.array_equal(got, want), f"frame {s}: {first_diff(got, want)}"
