@@ -57,11 +57,12 @@ def main() -> int:
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
-    ap.add_argument("--cpu-frames", type=int, default=16)
+    ap.add_argument("--cpu-frames", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--splat", choices=["auto", "direct", "binned"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--ppt", type=int, default=0)
+    ap.add_argument("--splits", type=int, default=0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -89,8 +90,8 @@ def main() -> int:
                                                      cams[0]))
     splat = {"auto": mm.MM_SPLAT_AUTO, "direct": mm.MM_SPLAT_DIRECT,
              "binned": mm.MM_SPLAT_BINNED}[args.splat]
-    if splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt:
-        mm.mm_set_tuning(view, splat, args.tile, args.ppt)
+    if splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits:
+        mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits)
     tuning = mm.mm_get_tuning(view)
     mode = "direct" if tuning[0] == mm.MM_SPLAT_DIRECT else "binned"
     print(f"bench: {n} points, {w}x{h}, warmup {W}, timed {K}, splat {mode} {tuning}",
@@ -133,7 +134,8 @@ def main() -> int:
         "config": {"workload": f"3d-uniform-2^{args.log2n}pts-{w}x{h}-orbit-1deg",
                    "points": n, "width": w, "height": h, "footprint": 1,
                    "amplitude": 0.001, "graph": "one hipGraph per frame",
-                   "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2]},
+                   "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2],
+                   "splits": tuning[3]},
         "frames_per_s": K / elapsed,
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),

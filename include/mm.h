@@ -150,9 +150,10 @@ mm_status mm_read_frame(mm_view view, void* host_rgba, size_t bytes);
  *    key buffer (skipped when a plain load already shows a smaller key),
  *    then a resolve pass over the screen.
  *  MM_SPLAT_BINNED: each workgroup sorts its points by screen tile in LDS
- *    and writes 8-byte records; then one workgroup per tile takes the
- *    per-pixel minimum in LDS and writes RGBA8 directly (3x3 footprints
- *    merge tile seams in a third pass). No global atomics.
+ *    and writes 8-byte records; then `splits` workgroups per tile take the
+ *    per-pixel minimum of their share in LDS, a merge pass combines them and
+ *    writes RGBA8 directly (3x3 footprints merge tile seams in a last pass).
+ *    No global atomics.
  *  MM_SPLAT_AUTO: binned when the screen fits the tile table, else direct. */
 #define MM_SPLAT_AUTO 0u
 #define MM_SPLAT_DIRECT 1u
@@ -162,6 +163,8 @@ typedef struct {
     uint32_t splat;             /* MM_SPLAT_* */
     uint32_t tile;              /* binned tile side: 16, 32 or 64 pixels; 0 = auto */
     uint32_t points_per_thread; /* binned: 4, 8 or 16 (workgroup of 256 threads); 0 = auto */
+    uint32_t splits;            /* binned: workgroups per tile in the depth test, 1, 2, 4
+                                   or 8 (each takes a share of the points); 0 = auto */
 } mm_tuning;
 
 /* Chooses the splat strategy and its shape for later frames; reallocates the

@@ -66,7 +66,8 @@ class mm_view_desc(C.Structure):
 
 
 class mm_tuning(C.Structure):
-    _fields_ = [("splat", C.c_uint32), ("tile", C.c_uint32), ("points_per_thread", C.c_uint32)]
+    _fields_ = [("splat", C.c_uint32), ("tile", C.c_uint32), ("points_per_thread", C.c_uint32),
+                ("splits", C.c_uint32)]
 
 
 _lib = None
@@ -208,16 +209,16 @@ def mm_destroy_view(view: int) -> None:
 
 
 def mm_set_tuning(view: int, splat: int = MM_SPLAT_AUTO, tile: int = 0,
-                  points_per_thread: int = 0) -> None:
-    t = mm_tuning(splat, tile, points_per_thread)
+                  points_per_thread: int = 0, splits: int = 0) -> None:
+    t = mm_tuning(splat, tile, points_per_thread, splits)
     _check(lib().mm_set_tuning(view, C.byref(t)), "mm_set_tuning")
 
 
-def mm_get_tuning(view: int) -> tuple[int, int, int]:
-    """(splat, tile, points_per_thread) in use."""
+def mm_get_tuning(view: int) -> tuple[int, int, int, int]:
+    """(splat, tile, points_per_thread, splits) in use."""
     t = mm_tuning()
     _check(lib().mm_get_tuning(view, C.byref(t)), "mm_get_tuning")
-    return t.splat, t.tile, t.points_per_thread
+    return t.splat, t.tile, t.points_per_thread, t.splits
 
 
 def mm_set_camera(view: int, view_proj) -> None:

@@ -12,13 +12,16 @@
 //   record = depth_bits << 32 | local_index << 16 | y_in_tile << 8 | x_in_tile
 //
 // tile kernel (one workgroup per screen tile):
-//   pull the tile's column of the table (one chunk per bin workgroup) into
-//   LDS, then read the chunks coalesced (a group of lanes per chunk, many
-//   chunks in flight), take the min (depth_bits << 32 | index) per pixel
-//   with LDS atomics, and resolve to RGBA8 directly: no full-screen key
-//   buffer, no clear pass. With the 3x3 footprint the LDS tile carries a
-//   one-pixel apron; edge pixels and the apron go to small global arrays,
-//   and the seam kernel merges edges across tile borders.
+//   (split into `splits` workgroups per tile, each over a share of the bin
+//   workgroups) pull the tile's column of the table into LDS, read the
+//   chunks coalesced (a group of lanes per chunk, many chunks in flight),
+//   take the min (depth_bits << 32 | index) per pixel with LDS atomics, and
+//   write the partial keys of the tile.
+// merge kernel (one workgroup per tile): min over the splits, resolve to
+//   RGBA8 directly: no full-screen key buffer, no clear pass. With the 3x3
+//   footprint the tile carries a one-pixel apron; edge pixels and the apron
+//   go to small global arrays, and the seam kernel merges edges across tile
+//   borders.
 #include "mm_device.h"
 
 namespace mm {
@@ -164,11 +167,15 @@ __global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
 }
 
 // 64 consecutive tiles share one 128-byte line of every table row; blocks go
-// round-robin over the 8 XCDs, so map each run of 64 tiles onto one XCD to
-// read every table line into one L2 once.
-__device__ __forceinline__ uint32_t tile_of_block(uint32_t b) {
+// round-robin over the 8 XCDs, so each run of 64 tiles (for one split of the
+// column) is mapped onto one XCD, to read every table line into one L2 once.
+// Block b -> (tile, split); the grid is ceil(ntiles / 512) * 512 * splits.
+__device__ __forceinline__ void tile_of_block(uint32_t b, uint32_t splits, uint32_t& t,
+                                              uint32_t& z) {
     const uint32_t x = b & 7u, k = b >> 3;
-    return ((k >> 6) * 8u + x) * 64u + (k & 63u);
+    const uint32_t q = k >> 6;
+    t = ((q / splits) * 8u + x) * 64u + (k & 63u);
+    z = q % splits;
 }
 
 // Position q on the ring of an (S+2)^2 apron tile <-> LDS coordinates.
@@ -229,33 +236,21 @@ __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
     constexpr uint32_t kPieces = 2;    // records per lane per chunk per round
     __shared__ uint64_t keys[A * A];
     __shared__ uint32_t col[kCol];     // start << 16 | count, per bin workgroup
-    const uint32_t t = tile_of_block(blockIdx.x);
+    uint32_t t, z;
+    tile_of_block(blockIdx.x, a.splits, t, z);
     if (t >= a.ntiles) return;
+    if (tile_flag(a, t) != *a.stamp_in) return;  // nothing to draw
     const uint32_t tid = threadIdx.x;
-    const uint32_t tx = t % a.tiles_x, ty = t / a.tiles_x;
-    const uint32_t x0 = tx << SHIFT, y0 = ty << SHIFT;
-    const uint32_t wt = min(S, a.width - x0), ht = min(S, a.height - y0);
-    uint32_t* out = a.colour + static_cast<uint64_t>(y0) * a.width + x0;
-
-    // Inactive tile: clear it if the previous frame drew it, else its pixels
-    // are already 0.
-    const uint32_t stamp = *a.stamp_in, flag = tile_flag(a, t);
-    if (flag != stamp) {
-        if (flag == stamp - 1u) {
-            for (uint32_t q = tid; q < S * S; q += 1024u) {
-                const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
-                if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * a.width + lx] = 0u;
-            }
-        }
-        return;
-    }
+    // this split takes bin workgroups [w_lo, w_hi)
+    const uint32_t w_lo = static_cast<uint32_t>(static_cast<uint64_t>(a.num_wg) * z / a.splits);
+    const uint32_t w_hi = static_cast<uint32_t>(static_cast<uint64_t>(a.num_wg) * (z + 1) / a.splits);
     for (uint32_t q = tid; q < A * A; q += 1024u) keys[q] = kEmptyKey;
     const uint32_t group = tid / kGroup, sub = tid % kGroup;
     const uint32_t stride = a.ntiles + 1u;
     const uint32_t P = a.points_per_wg;
 
-    for (uint32_t base = 0; base < a.num_wg; base += kCol) {
-        const uint32_t nb = min(kCol, a.num_wg - base);
+    for (uint32_t base = w_lo; base < w_hi; base += kCol) {
+        const uint32_t nb = min(kCol, w_hi - base);
         __syncthreads();  // keys initialised / previous pass done with col
         uint32_t cs[kCol / 1024], ce[kCol / 1024];
 #pragma unroll
@@ -316,14 +311,51 @@ __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
         }
     }
     __syncthreads();
+    uint64_t* part = a.part + (static_cast<uint64_t>(t) * a.splits + z) * (A * A);
+    for (uint32_t q = tid; q < A * A; q += 1024u) part[q] = keys[q];
+}
 
-    for (uint32_t q = tid; q < S * S; q += 1024u) {
+// Per tile: the minimum of the splits' partial keys, then RGBA8 (edge keys and
+// the apron of 3x3 footprints go to the seam pass). A tile with nothing to
+// draw is cleared if the previous frame drew it; otherwise its pixels are
+// already 0.
+template <int FOOT, int SHIFT>
+__global__ __launch_bounds__(256) void merge_kernel(TileArgs a) {
+    constexpr uint32_t S = 1u << SHIFT;
+    constexpr uint32_t A = FOOT == 3 ? S + 2 : S;
+    const uint32_t t = blockIdx.x;
+    if (t >= a.ntiles) return;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t tx = t % a.tiles_x, ty = t / a.tiles_x;
+    const uint32_t x0 = tx << SHIFT, y0 = ty << SHIFT;
+    const uint32_t wt = min(S, a.width - x0), ht = min(S, a.height - y0);
+    uint32_t* out = a.colour + static_cast<uint64_t>(y0) * a.width + x0;
+    const uint32_t stamp = *a.stamp_in, flag = tile_flag(a, t);
+    if (flag != stamp) {
+        if (flag == stamp - 1u) {
+            for (uint32_t q = tid; q < S * S; q += 256u) {
+                const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
+                if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * a.width + lx] = 0u;
+            }
+        }
+        return;
+    }
+    const uint64_t* part = a.part + static_cast<uint64_t>(t) * a.splits * (A * A);
+    auto key_at = [&](uint32_t q) {
+        uint64_t k = part[q];
+        for (uint32_t z = 1; z < a.splits; ++z) {
+            const uint64_t v = part[static_cast<uint64_t>(z) * (A * A) + q];
+            k = v < k ? v : k;
+        }
+        return k;
+    };
+    for (uint32_t q = tid; q < S * S; q += 256u) {
         const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
         if (lx >= wt || ly >= ht) continue;
         if constexpr (FOOT == 1) {
-            out[static_cast<uint64_t>(ly) * a.width + lx] = colour_of(keys[q], a.seed_lo, a.seed_hi);
+            out[static_cast<uint64_t>(ly) * a.width + lx] = colour_of(key_at(q), a.seed_lo, a.seed_hi);
         } else {
-            const uint64_t k = keys[(ly + 1) * A + lx + 1];
+            const uint64_t k = key_at((ly + 1) * A + lx + 1);
             if (lx == 0 || ly == 0 || lx == S - 1 || ly == S - 1) {
                 uint64_t* bd = a.border + static_cast<uint64_t>(t) * (4 * S);
                 if (ly == 0) bd[lx] = k;
@@ -337,10 +369,10 @@ __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
     }
     if constexpr (FOOT == 3) {
         uint64_t* ap = a.apron + static_cast<uint64_t>(t) * (4 * S + 4);
-        for (uint32_t q = tid; q < 4 * S + 4; q += 1024u) {
+        for (uint32_t q = tid; q < 4 * S + 4; q += 256u) {
             uint32_t ax, ay;
             ring_coord<S>(q, ax, ay);
-            ap[q] = keys[ay * A + ax];
+            ap[q] = key_at(ay * A + ax);
         }
     }
 }
@@ -430,8 +462,9 @@ const void* pick_tile(int shift) {
 
 }  // namespace
 
-bool binned_shape_ok(int shift, int ppt) {
-    return (shift == 4 || shift == 5 || shift == 6) && (ppt == 4 || ppt == 8 || ppt == 16);
+bool binned_shape_ok(int shift, int ppt, uint32_t splits) {
+    return (shift == 4 || shift == 5 || shift == 6) && (ppt == 4 || ppt == 8 || ppt == 16) &&
+           (splits == 1 || splits == 2 || splits == 4 || splits == 8);
 }
 
 size_t bin_lds_bytes(int ppt, uint32_t ntiles) {
@@ -451,11 +484,27 @@ Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t n, uint32_t
     return l;
 }
 
-Launch tile_launch(int footprint, int shift, uint32_t ntiles) {
+Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits) {
     Launch l;
     l.func = footprint == 3 ? pick_tile<3>(shift) : pick_tile<1>(shift);
     l.block = dim3(1024);
-    l.grid = dim3((ntiles + 511u) / 512u * 512u);  // whole runs of 8 XCDs x 64 tiles
+    l.grid = dim3((ntiles + 511u) / 512u * 512u * splits);  // whole runs of 8 XCDs x 64 tiles
+    l.shared = 0;
+    return l;
+}
+
+Launch merge_launch(int footprint, int shift, uint32_t ntiles) {
+    Launch l;
+    if (footprint == 3)
+        l.func = shift == 4 ? reinterpret_cast<const void*>(&merge_kernel<3, 4>)
+               : shift == 5 ? reinterpret_cast<const void*>(&merge_kernel<3, 5>)
+                            : reinterpret_cast<const void*>(&merge_kernel<3, 6>);
+    else
+        l.func = shift == 4 ? reinterpret_cast<const void*>(&merge_kernel<1, 4>)
+               : shift == 5 ? reinterpret_cast<const void*>(&merge_kernel<1, 5>)
+                            : reinterpret_cast<const void*>(&merge_kernel<1, 6>);
+    l.block = dim3(256);
+    l.grid = dim3(ntiles);
     l.shared = 0;
     return l;
 }

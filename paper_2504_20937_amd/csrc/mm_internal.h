@@ -50,12 +50,14 @@ struct TileArgs {
     const uint16_t* table;
     const uint32_t* active;
     const uint32_t* stamp_in;
+    uint64_t* part;      // ntiles * splits partial key tiles (apron included)
     uint64_t* border;    // footprint 3: ntiles * 4 * side edge keys
     uint64_t* apron;     // footprint 3: ntiles * (4 * side + 4) apron keys
     uint32_t* colour;
     uint32_t width, height;
     uint32_t tiles_x, tiles_y, ntiles;
     uint32_t num_wg, points_per_wg;
+    uint32_t splits;     // tile-pass workgroups per tile
     uint32_t seed_lo, seed_hi;
 };
 
@@ -77,11 +79,12 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_fill(uint64_t* keys, uint64_t nkeys, uint64_t value, hipStream_t s);
 
 // Binned splat. Tile side 1 << shift with shift in {4, 5, 6}; points per
-// thread in {4, 8, 16}.
-bool binned_shape_ok(int shift, int ppt);
+// thread in {4, 8, 16}; splits per tile in {1, 2, 4, 8}.
+bool binned_shape_ok(int shift, int ppt, uint32_t splits);
 size_t bin_lds_bytes(int ppt, uint32_t ntiles);
 Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t n, uint32_t ntiles);
-Launch tile_launch(int footprint, int shift, uint32_t ntiles);
+Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits);
+Launch merge_launch(int footprint, int shift, uint32_t ntiles);
 Launch seam_launch(int shift, uint32_t ntiles);
 
 }  // namespace mm

@@ -52,6 +52,7 @@ struct mm_view_s {
     uint64_t* seg = nullptr;
     uint16_t* table = nullptr;
     uint32_t* active = nullptr;  // ntiles stamps + 1 slot for the frame stamp
+    uint64_t* part = nullptr;
     uint64_t* border = nullptr;
     uint64_t* apron = nullptr;
     uint32_t tiles_x = 0, tiles_y = 0, ntiles = 0, num_wg = 0, stamp = 0;
@@ -213,12 +214,14 @@ mm_status build_graph(mm_view v, bool timed, FrameGraph& out) {
 void free_splat_buffers(mm_view v) {
     for (void* p : {static_cast<void*>(v->depth), static_cast<void*>(v->seg),
                     static_cast<void*>(v->table), static_cast<void*>(v->active),
-                    static_cast<void*>(v->border), static_cast<void*>(v->apron)})
+                    static_cast<void*>(v->part), static_cast<void*>(v->border),
+                    static_cast<void*>(v->apron)})
         if (p) (void)hipFree(p);
     v->depth = nullptr;
     v->seg = nullptr;
     v->table = nullptr;
     v->active = nullptr;
+    v->part = nullptr;
     v->border = nullptr;
     v->apron = nullptr;
 }
@@ -237,13 +240,23 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
     if (out.splat == MM_SPLAT_DIRECT) {
         out.tile = 0;
         out.points_per_thread = 0;
+        out.splits = 0;
         return MM_OK;
     }
     if (out.tile == 0) out.tile = tiles(32) <= 4096u ? 32u : 64u;
     if (out.points_per_thread == 0) out.points_per_thread = 16;
-    if (!mm::binned_shape_ok(static_cast<int>(shift_of(out.tile)), static_cast<int>(out.points_per_thread)))
-        return fail(MM_ERR_INVALID_ARG, "tuning: tile %u / points_per_thread %u not in {16,32,64} x {4,8,16}",
-                    out.tile, out.points_per_thread);
+    if (out.splits == 0) {
+        // enough workgroups per tile to spread the densest tiles over the
+        // chip once the bin workgroups are many
+        const uint64_t wgs = (d.element_count + 256ull * out.points_per_thread - 1) /
+                             (256ull * out.points_per_thread);
+        out.splits = wgs >= 256 ? 2u : 1u;
+    }
+    if (!mm::binned_shape_ok(static_cast<int>(shift_of(out.tile)), static_cast<int>(out.points_per_thread),
+                             out.splits))
+        return fail(MM_ERR_INVALID_ARG,
+                    "tuning: tile %u / points_per_thread %u / splits %u not in {16,32,64} x {4,8,16} x {1,2,4,8}",
+                    out.tile, out.points_per_thread, out.splits);
     if (tiles(out.tile) > 4096u)
         return fail(MM_ERR_UNSUPPORTED, "tuning: %ux%u screen needs %u tiles of %u px (max 4096)",
                     d.width, d.height, tiles(out.tile), out.tile);
@@ -286,6 +299,9 @@ mm_status setup_splat(mm_view v) {
         if (e == hipSuccess) e = alloc_n(&v->active, static_cast<uint64_t>(v->ntiles) + 1);
         if (e == hipSuccess)
             e = hipMemsetAsync(v->active, 0, (static_cast<size_t>(v->ntiles) + 1) * 4, inst->stream);
+        const uint64_t side_a = foot == 3 ? side + 2 : side;
+        if (e == hipSuccess)
+            e = alloc_n(&v->part, static_cast<uint64_t>(v->ntiles) * v->tuning.splits * side_a * side_a);
         if (e == hipSuccess && foot == 3) {
             e = alloc_n(&v->border, static_cast<uint64_t>(v->ntiles) * 4 * side);
             if (e == hipSuccess) e = alloc_n(&v->apron, static_cast<uint64_t>(v->ntiles) * (4 * side + 4));
@@ -308,6 +324,7 @@ mm_status setup_splat(mm_view v) {
         t.table = v->table;
         t.active = v->active;
         t.stamp_in = v->active + v->ntiles;
+        t.part = v->part;
         t.border = v->border;
         t.apron = v->apron;
         t.colour = v->colour;
@@ -318,10 +335,12 @@ mm_status setup_splat(mm_view v) {
         t.ntiles = v->ntiles;
         t.num_wg = v->num_wg;
         t.points_per_wg = static_cast<uint32_t>(P);
+        t.splits = v->tuning.splits;
         t.seed_lo = v->args.seed_lo;
         t.seed_hi = v->args.seed_hi;
         v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, v->args.n, v->ntiles));
-        v->nodes.push_back(mm::tile_launch(foot, static_cast<int>(shift), v->ntiles));
+        v->nodes.push_back(mm::tile_launch(foot, static_cast<int>(shift), v->ntiles, v->tuning.splits));
+        v->nodes.push_back(mm::merge_launch(foot, static_cast<int>(shift), v->ntiles));
         if (foot == 3) v->nodes.push_back(mm::seam_launch(static_cast<int>(shift), v->ntiles));
     }
     return build_graph(v, false, v->plain);
