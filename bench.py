@@ -26,8 +26,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "displace+render Gpoints/s & frames/s @2^24 pts 1080p; p99 frame latency"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2504_20937_amd", "csrc")
+
+# HBM traffic of the dominant kernel per launch, from rocprofv3 --pmc runs of
+# this benchmark's default workload (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), scaled by what the same counters read for a plain 256 MiB device
+# copy (FETCH_SIZE reads half the copied bytes: x2; WRITE_SIZE reads them
+# all: x1). Keyed by a digest of the kernel sources: any change to them makes
+# the entry stale and the reported traffic null until it is measured again.
+TRAFFIC = {
+    "bin_kernel": {"digest": "1be659fb7853545d", "fetch_kib": 98450.0, "write_kib": 344200.0,
+                   "fetch_scale": 2.0, "write_scale": 1.0},
+}
 POINT_BYTES = 24   # float3 read + write per point and frame
 PIXEL_BYTES = 20   # key read + empty-key write (8 + 8) and RGBA8 write (4)
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    e = TRAFFIC.get(kernel)
+    if not e or e["digest"] != kernel_digest():
+        return None
+    return (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"]) * 1024.0
 
 
 def cpu_baseline(n, w, h, frames):
@@ -63,6 +93,9 @@ def main() -> int:
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--ppt", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run 10 plain device copies of BYTES (for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -77,6 +110,16 @@ def main() -> int:
     import synth
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n4 = args.calibrate_copy // 4
+        src = torch.ones(n4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n4 * 4, "launches": 10}), flush=True)
+        return 0
     n, w, h = 1 << args.log2n, args.width, args.height
     K, W = args.steps, args.warmup
     pts = synth.uniform_cube(n, 0)
@@ -142,7 +185,8 @@ def main() -> int:
         "point_kernel_ms": splat_avg,
         "rest_of_frame_ms": float(np.mean(resolve_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("bin_kernel") if mode == "binned" else None,
                      "kernel": ("bin_kernel (displace+project+tile sort)" if mode == "binned"
                                 else "point_kernel (displace+project+splat)"),
                      "bytes_per_launch": point_bytes},
