@@ -79,6 +79,144 @@ def cpu_baseline(n, w, h, frames):
             "ms_per_frame": dt / frames * 1e3}
 
 
+def batch_workload(seed: int = 0):
+    """64 clouds of round(2^U[12,22]) points (uniform if even, Gaussian mixture
+    if odd), each with 1-4 square views at 256, 512 or 1024 px and its own
+    orbit start angle."""
+    import synth
+    specs = synth.batched_set(64, seed=seed)
+    return specs, [synth.cloud_points(sp) for sp in specs]
+
+
+def bench_batched(args) -> dict:
+    """One batch frame (every cloud displaced, every view rendered) per graph
+    launch, against the same work as plain views: per cloud, mm_step_render
+    on its first view and mm_render on its other views."""
+    import torch
+
+    import paper_2504_20937_amd as mm
+    import synth
+
+    specs, pts = batch_workload()
+    K, W = args.steps, args.warmup
+    stream = torch.cuda.current_stream()
+    inst = mm.mm_create_instance(0, stream.cuda_stream)
+    devs, allocs, clouds, views, vinfo = [], [], [], [], []
+    for j, (sp, p) in enumerate(zip(specs, pts)):
+        d = torch.from_numpy(p).cuda()
+        a = mm.mm_alloc_wrap(inst, d.data_ptr(), d.numel() * 4)
+        devs.append(d)
+        allocs.append(a)
+        clouds.append(mm.make_cloud_desc(a, p.shape[0], 3, sp.seed, 0.001, False))
+        for (vw, vh, deg) in sp.views:
+            views.append(mm.make_batch_view_desc(j, vw, vh, synth.orbit_camera(0, vw, vh, start_deg=deg)))
+            vinfo.append((j, vw, vh, deg))
+    total_pts = sum(p.shape[0] for p in pts)
+    total_px = sum(vw * vh for _, vw, vh, _ in vinfo)
+    del pts
+
+    def cams(f):
+        return [synth.orbit_camera(f, vw, vh, start_deg=deg) for _, vw, vh, deg in vinfo]
+
+    frames_cams = [np.ascontiguousarray(np.stack(cams(f)), dtype=np.float32) for f in range(W + K)]
+    b = mm.mm_create_batch(inst, 3, 1, clouds, views)
+    if args.autotune:
+        mm.mm_batch_autotune(b, 5)
+    elif args.tile or args.ppt or args.splits or args.grid:
+        mm.mm_batch_set_tuning(b, args.tile, args.ppt, args.splits, args.grid)
+    tuning = mm.mm_batch_get_tuning(b)
+    print(f"bench batched: {len(clouds)} clouds, {total_pts} points, {len(views)} views, "
+          f"{total_px} px, tuning {tuning}", file=sys.stderr, flush=True)
+
+    def batch_frame(f):
+        mm.mm_batch_set_cameras(b, 0, frames_cams[f])
+        mm.mm_batch_step_render(b, f)
+
+    for f in range(W):
+        batch_frame(f)
+    mm.mm_batch_profile_begin(b, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        batch_frame(W + k)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    frame_ms = mm.mm_batch_profile_end(b, K)
+    mm.mm_destroy_batch(b)
+
+    # the same frames as plain views: a graph per cloud (displace + first
+    # view) and a render per further view
+    pv = []
+    for k, (j, vw, vh, deg) in enumerate(vinfo):
+        d = mm.make_view_desc(allocs[j], devs[j].shape[0], 3, vw, vh, 1, specs[j].seed, 0.001,
+                              False, frames_cams[0][k])
+        v = mm.mm_create_view(inst, d)
+        mm.mm_set_tuning(v, mm.MM_SPLAT_BINNED)
+        pv.append(v)
+    first = {}
+    for k, (j, _, _, _) in enumerate(vinfo):
+        first.setdefault(j, k)
+
+    # raw library calls with prepared arguments: the host loop costs about what
+    # a C caller's would
+    L = mm.lib()
+    import ctypes as C
+    fp = C.POINTER(C.c_float)
+    cam_ptrs = [[frames_cams[f][k].ctypes.data_as(fp) for k in range(len(pv))]
+                for f in range(W + K)]
+    is_first = [first[vinfo[k][0]] == k for k in range(len(pv))]
+
+    def plain_frame(f):
+        cp = cam_ptrs[f]
+        for k, v in enumerate(pv):
+            L.mm_set_camera(v, cp[k])
+            if is_first[k]:
+                L.mm_step_render(v, f)
+            else:
+                L.mm_render(v)
+
+    for f in range(min(W, 5)):
+        plain_frame(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        plain_frame(W + k)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for v in pv:
+        mm.mm_destroy_view(v)
+    for a in allocs:
+        mm.mm_free(a)
+    mm.mm_destroy_instance(inst)
+    point_bytes = POINT_BYTES * total_pts
+    batch_bytes = point_bytes + 4 * total_px
+    return {
+        "metric": "batched displace+render Gpoints/s & frames/s, 64 clouds (2^12..2^22 pts), "
+                  "1-4 views each; vs plain launches",
+        "value": total_pts * K / t_batch / 1e9,
+        "unit": "Gpoints/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": t_batch / K * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched-64-clouds-2^12..2^22-1..4-views-256/512/1024",
+                   "clouds": len(clouds), "points": total_pts, "views": len(views),
+                   "pixels": total_px, "tile": tuning[0], "points_per_thread": tuning[1],
+                   "splits": tuning[2], "grid_blocks": tuning[3]},
+        "frames_per_s": K / t_batch,
+        "views_per_s": K * len(views) / t_batch,
+        "p50_frame_ms": float(np.percentile(frame_ms, 50)),
+        "p99_frame_ms": float(np.percentile(frame_ms, 99)),
+        "plain": {"value": total_pts * K / t_plain / 1e9, "unit": "Gpoints/s",
+                  "ms_per_step": t_plain / K * 1e3, "frames_per_s": K / t_plain,
+                  "launches_per_frame": len(views)},
+        "speedup_vs_plain": t_plain / t_batch,
+        "frame_roofline": {"bytes_per_frame": batch_bytes,
+                           "achieved_GBps": batch_bytes / (t_batch / K) / 1e9,
+                           "frac": batch_bytes / (t_batch / K) / 1e9 / HBM_PEAK_GBS},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +231,11 @@ def main() -> int:
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--ppt", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0, help="batched: persistent grid blocks")
+    ap.add_argument("--autotune", action="store_true", help="time the shapes, keep the fastest")
+    ap.add_argument("--workload", choices=["frame", "batched"], default="frame",
+                    help="frame: the 2^24-point 1080p frame (default); batched: 64 clouds "
+                         "with 1-4 views each in one launch per pass")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device copies of BYTES (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -120,6 +263,9 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n4 * 4, "launches": 10}), flush=True)
         return 0
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return 0
     n, w, h = 1 << args.log2n, args.width, args.height
     K, W = args.steps, args.warmup
     pts = synth.uniform_cube(n, 0)
@@ -133,7 +279,9 @@ def main() -> int:
                                                      cams[0]))
     splat = {"auto": mm.MM_SPLAT_AUTO, "direct": mm.MM_SPLAT_DIRECT,
              "binned": mm.MM_SPLAT_BINNED}[args.splat]
-    if splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits:
+    if args.autotune:
+        mm.mm_autotune(view, 10)
+    elif splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits:
         mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits)
     tuning = mm.mm_get_tuning(view)
     mode = "direct" if tuning[0] == mm.MM_SPLAT_DIRECT else "binned"

@@ -40,6 +40,8 @@ extern "C" {
 typedef struct mm_instance_s* mm_instance;
 typedef struct mm_alloc_s* mm_alloc;
 typedef struct mm_view_s* mm_view;
+typedef struct mm_batch_s* mm_batch;
+typedef struct mm_server_s* mm_server;
 
 typedef int32_t mm_status;
 #define MM_OK 0
@@ -176,6 +178,17 @@ mm_status mm_set_tuning(mm_view view, const mm_tuning* tuning);
 /* The resolved strategy and shape in use (never MM_SPLAT_AUTO or 0). */
 mm_status mm_get_tuning(mm_view view, mm_tuning* out);
 
+/* Autotuning: times every supported strategy and shape on `frames` whole
+ * frames (mm_step_render with step 0, after one warm-up frame; frames in
+ * [1, 1000]) and keeps the fastest, which *out receives (resolved). The
+ * positions are saved first and restored afterwards, so the cloud is left as
+ * it was; the frame holds the last timed frame. When the environment
+ * variable MM_TUNE_CACHE names a file, a shape found before for the same
+ * device architecture, point count, screen, domain and footprint is taken
+ * from it without timing, and new results are appended to it.
+ * Synchronises. */
+mm_status mm_autotune(mm_view view, uint32_t frames, mm_tuning* out);
+
 /* Per-kernel timing of the next frames, for measurement. mm_profile_begin
  * makes the view's next `capacity` calls of mm_step_render record HIP
  * events inside the frame graph: before and after the point pass (displace,
@@ -188,6 +201,100 @@ mm_status mm_get_tuning(mm_view view, mm_tuning* out);
 mm_status mm_profile_begin(mm_view view, uint32_t capacity);
 mm_status mm_profile_end(mm_view view, float* splat_ms, float* resolve_ms, float* frame_ms,
                          uint32_t* count);
+
+/* ----------------------------------------------------------------- batches
+ * Many point clouds, each drawn into one or more views, rendered together
+ * with one launch per pass of the binned splat (the per-frame loop of
+ * section "Synchronization" over many views at once). A bin work item is a
+ * chunk of one cloud: it is displaced once and then binned into every view
+ * of its cloud. Each (cloud, view) frame is bit-identical to the frame of a
+ * plain view (mm_view_desc with the cloud's fields and the view's screen
+ * and camera) after the same steps. */
+typedef struct {
+    mm_alloc position;      /* element_count points, AoS; no two clouds of a batch
+                               may share an alloc */
+    uint64_t element_count; /* 1 <= N <= 2^32 - 1; N * stride must fit the alloc */
+    mm_format format;       /* MM_FLOAT2 with MM_DOMAIN_2D, MM_FLOAT3 with MM_DOMAIN_3D */
+    uint64_t seed;          /* key of the displacement draw and of the colour hash */
+    float amplitude;        /* as mm_view_desc.amplitude */
+    int32_t wrap;           /* as mm_view_desc.wrap */
+} mm_cloud_desc;
+
+typedef struct {
+    uint32_t cloud;         /* index into mm_batch_desc.clouds */
+    uint32_t width;         /* even, in [2, 16384]; at most 4096 tiles of 64 px */
+    uint32_t height;
+    float view_proj[16];    /* row-major float32 clip-from-world matrix; 3D only */
+} mm_batch_view_desc;
+
+typedef struct {
+    mm_domain domain;       /* of every cloud */
+    uint32_t footprint;     /* marker side of every view: 1 or 3 */
+    uint32_t n_clouds;      /* >= 1 */
+    const mm_cloud_desc* clouds;
+    uint32_t n_views;       /* >= 1; a cloud may have no view (it is only displaced) */
+    const mm_batch_view_desc* views;
+} mm_batch_desc;
+
+/* Creates a batch: validates desc, allocates one RGBA8 frame (zero) per view
+ * and the binned-splat scratch of every view, writes the work tables to
+ * device memory and builds the batch's frame graph. Views are addressed by
+ * their index in desc->views. The batch refers to the clouds' allocs until
+ * destroyed. */
+mm_status mm_create_batch(mm_instance inst, const mm_batch_desc* desc, mm_batch* out);
+
+/* Frees the batch (after the stream has drained). */
+mm_status mm_destroy_batch(mm_batch batch);
+
+/* Replaces the camera of view `view` for later frames. */
+mm_status mm_batch_set_camera(mm_batch batch, uint32_t view, const float view_proj[16]);
+
+/* Replaces the cameras of views first .. first + count - 1 from count
+ * consecutive row-major 4x4 matrices (16 * count floats). */
+mm_status mm_batch_set_cameras(mm_batch batch, uint32_t first, uint32_t count,
+                               const float* view_proj);
+
+/* One frame of the whole batch: every cloud is displaced with `step`, then
+ * every view is splatted and resolved. One graph launch (after a small
+ * host-to-device copy of the per-frame cameras and steps). */
+mm_status mm_batch_step_render(mm_batch batch, uint32_t step);
+
+/* Render only (no displacement), launched kernel by kernel. */
+mm_status mm_batch_render(mm_batch batch);
+
+/* Device address of view `view`'s frame, valid until the batch is destroyed. */
+mm_status mm_batch_frame_device_ptr(mm_batch batch, uint32_t view, const uint32_t** dev_rgba);
+
+/* Copies view `view`'s frame to host memory (bytes >= width * height * 4).
+ * Synchronises. */
+mm_status mm_batch_read_frame(mm_batch batch, uint32_t view, void* host_rgba, size_t bytes);
+
+typedef struct {
+    uint32_t tile;              /* tile side of every view: 16, 32 or 64; 0 = auto */
+    uint32_t points_per_thread; /* 4, 8 or 16; 0 = auto */
+    uint32_t splits;            /* workgroups per tile: 1, 2, 4 or 8 for every view;
+                                   0 = per view by the size of its cloud */
+    uint32_t grid_blocks;       /* 0: one workgroup per work item; else a persistent
+                                   grid of that many workgroups per pass, each
+                                   looping over work items */
+} mm_batch_tuning;
+
+/* Chooses the shape for later frames; reallocates scratch and rebuilds the
+ * graph. Synchronises. */
+mm_status mm_batch_set_tuning(mm_batch batch, const mm_batch_tuning* tuning);
+mm_status mm_batch_get_tuning(mm_batch batch, mm_batch_tuning* out);
+
+/* Autotuning of a batch, as mm_autotune: every supported tile, points per
+ * thread, splits and grid shape is timed on `frames` whole batch frames and
+ * the fastest is kept; every cloud's positions are restored afterwards.
+ * The cache key is the device architecture and a hash of the cloud sizes,
+ * the views' clouds and screens, the domain and the footprint. */
+mm_status mm_batch_autotune(mm_batch batch, uint32_t frames, mm_batch_tuning* out);
+
+/* Frame timing of the next `capacity` calls of mm_batch_step_render: HIP
+ * events before the per-frame upload and after the frame graph. */
+mm_status mm_batch_profile_begin(mm_batch batch, uint32_t capacity);
+mm_status mm_batch_profile_end(mm_batch batch, float* frame_ms, uint32_t* count);
 
 /* ------------------------------------------------------------ diagnostics */
 const char* mm_status_string(mm_status status);

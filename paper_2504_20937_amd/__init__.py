@@ -70,6 +70,42 @@ class mm_tuning(C.Structure):
                 ("splits", C.c_uint32)]
 
 
+class mm_cloud_desc(C.Structure):
+    _fields_ = [
+        ("position", C.c_void_p),
+        ("element_count", C.c_uint64),
+        ("format", C.c_int),
+        ("seed", C.c_uint64),
+        ("amplitude", C.c_float),
+        ("wrap", C.c_int32),
+    ]
+
+
+class mm_batch_view_desc(C.Structure):
+    _fields_ = [
+        ("cloud", C.c_uint32),
+        ("width", C.c_uint32),
+        ("height", C.c_uint32),
+        ("view_proj", C.c_float * 16),
+    ]
+
+
+class mm_batch_desc(C.Structure):
+    _fields_ = [
+        ("domain", C.c_int),
+        ("footprint", C.c_uint32),
+        ("n_clouds", C.c_uint32),
+        ("clouds", C.POINTER(mm_cloud_desc)),
+        ("n_views", C.c_uint32),
+        ("views", C.POINTER(mm_batch_view_desc)),
+    ]
+
+
+class mm_batch_tuning(C.Structure):
+    _fields_ = [("tile", C.c_uint32), ("points_per_thread", C.c_uint32), ("splits", C.c_uint32),
+                ("grid_blocks", C.c_uint32)]
+
+
 _lib = None
 _status = C.c_int32
 _vp = C.c_void_p
@@ -99,6 +135,20 @@ def _declare(L):
         "mm_profile_begin": ([_vp, C.c_uint32], _status),
         "mm_profile_end": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
                             C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
+        "mm_autotune": ([_vp, C.c_uint32, C.POINTER(mm_tuning)], _status),
+        "mm_batch_autotune": ([_vp, C.c_uint32, C.POINTER(mm_batch_tuning)], _status),
+        "mm_create_batch": ([_vp, C.POINTER(mm_batch_desc), C.POINTER(_vp)], _status),
+        "mm_destroy_batch": ([_vp], _status),
+        "mm_batch_set_camera": ([_vp, C.c_uint32, C.POINTER(C.c_float)], _status),
+        "mm_batch_set_cameras": ([_vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_float)], _status),
+        "mm_batch_step_render": ([_vp, C.c_uint32], _status),
+        "mm_batch_render": ([_vp], _status),
+        "mm_batch_frame_device_ptr": ([_vp, C.c_uint32, C.POINTER(_vp)], _status),
+        "mm_batch_read_frame": ([_vp, C.c_uint32, _vp, C.c_size_t], _status),
+        "mm_batch_set_tuning": ([_vp, C.POINTER(mm_batch_tuning)], _status),
+        "mm_batch_get_tuning": ([_vp, C.POINTER(mm_batch_tuning)], _status),
+        "mm_batch_profile_begin": ([_vp, C.c_uint32], _status),
+        "mm_batch_profile_end": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -221,6 +271,13 @@ def mm_get_tuning(view: int) -> tuple[int, int, int, int]:
     return t.splat, t.tile, t.points_per_thread, t.splits
 
 
+def mm_autotune(view: int, frames: int = 10) -> tuple[int, int, int, int]:
+    """Times the supported shapes, keeps the fastest; returns it as mm_get_tuning does."""
+    t = mm_tuning()
+    _check(lib().mm_autotune(view, frames, C.byref(t)), "mm_autotune")
+    return t.splat, t.tile, t.points_per_thread, t.splits
+
+
 def mm_set_camera(view: int, view_proj) -> None:
     m = np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(16))
     _check(lib().mm_set_camera(view, _fptr(m)), "mm_set_camera")
@@ -265,3 +322,109 @@ def mm_profile_end(view: int, capacity: int):
            "mm_profile_end")
     k = n.value
     return s[:k], r[:k], f[:k]
+
+
+# ------------------------------------------------------------------- batches
+def make_cloud_desc(position: int, element_count: int, dim: int, seed: int = 0,
+                    amplitude: float = 0.0, wrap: bool = False) -> mm_cloud_desc:
+    c = mm_cloud_desc()
+    c.position = position
+    c.element_count = element_count
+    c.format = MM_FLOAT2 if dim == 2 else MM_FLOAT3
+    c.seed = seed
+    c.amplitude = amplitude
+    c.wrap = int(bool(wrap))
+    return c
+
+
+def make_batch_view_desc(cloud: int, width: int, height: int,
+                         view_proj=None) -> mm_batch_view_desc:
+    v = mm_batch_view_desc()
+    v.cloud, v.width, v.height = cloud, width, height
+    m = np.eye(4, dtype=np.float32) if view_proj is None else view_proj
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(16))
+    for k in range(16):
+        v.view_proj[k] = float(m[k])
+    return v
+
+
+def mm_create_batch(inst: int, dim: int, footprint: int, clouds, views) -> int:
+    """clouds: sequence of mm_cloud_desc; views: sequence of mm_batch_view_desc."""
+    ca = (mm_cloud_desc * max(1, len(clouds)))(*clouds)
+    va = (mm_batch_view_desc * max(1, len(views)))(*views)
+    d = mm_batch_desc()
+    d.domain = MM_DOMAIN_2D if dim == 2 else MM_DOMAIN_3D
+    d.footprint = footprint
+    d.n_clouds, d.clouds = len(clouds), ca
+    d.n_views, d.views = len(views), va
+    out = _vp()
+    _check(lib().mm_create_batch(inst, C.byref(d), C.byref(out)), "mm_create_batch")
+    return out.value
+
+
+def mm_destroy_batch(batch: int) -> None:
+    _check(lib().mm_destroy_batch(batch), "mm_destroy_batch")
+
+
+def mm_batch_set_camera(batch: int, view: int, view_proj) -> None:
+    m = np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(16))
+    _check(lib().mm_batch_set_camera(batch, view, _fptr(m)), "mm_batch_set_camera")
+
+
+def mm_batch_set_cameras(batch: int, first: int, view_proj) -> None:
+    """view_proj: (count, 4, 4) or (count, 16) float32, for views first.. first+count-1."""
+    m = np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(-1, 16))
+    _check(lib().mm_batch_set_cameras(batch, first, m.shape[0], _fptr(m)), "mm_batch_set_cameras")
+
+
+def mm_batch_step_render(batch: int, step: int) -> None:
+    _check(lib().mm_batch_step_render(batch, step), "mm_batch_step_render")
+
+
+def mm_batch_render(batch: int) -> None:
+    _check(lib().mm_batch_render(batch), "mm_batch_render")
+
+
+def mm_batch_frame_device_ptr(batch: int, view: int) -> int:
+    out = _vp()
+    _check(lib().mm_batch_frame_device_ptr(batch, view, C.byref(out)),
+           "mm_batch_frame_device_ptr")
+    return out.value
+
+
+def mm_batch_read_frame(batch: int, view: int, width: int, height: int) -> np.ndarray:
+    out = np.empty((height, width), dtype=np.uint32)
+    _check(lib().mm_batch_read_frame(batch, view, out.ctypes.data, out.nbytes),
+           "mm_batch_read_frame")
+    return out
+
+
+def mm_batch_set_tuning(batch: int, tile: int = 0, points_per_thread: int = 0, splits: int = 0,
+                        grid_blocks: int = 0) -> None:
+    t = mm_batch_tuning(tile, points_per_thread, splits, grid_blocks)
+    _check(lib().mm_batch_set_tuning(batch, C.byref(t)), "mm_batch_set_tuning")
+
+
+def mm_batch_get_tuning(batch: int) -> tuple[int, int, int, int]:
+    """(tile, points_per_thread, splits, grid_blocks) in use."""
+    t = mm_batch_tuning()
+    _check(lib().mm_batch_get_tuning(batch, C.byref(t)), "mm_batch_get_tuning")
+    return t.tile, t.points_per_thread, t.splits, t.grid_blocks
+
+
+def mm_batch_autotune(batch: int, frames: int = 5) -> tuple[int, int, int, int]:
+    t = mm_batch_tuning()
+    _check(lib().mm_batch_autotune(batch, frames, C.byref(t)), "mm_batch_autotune")
+    return t.tile, t.points_per_thread, t.splits, t.grid_blocks
+
+
+def mm_batch_profile_begin(batch: int, capacity: int) -> None:
+    _check(lib().mm_batch_profile_begin(batch, capacity), "mm_batch_profile_begin")
+
+
+def mm_batch_profile_end(batch: int, capacity: int) -> np.ndarray:
+    """Frame times (ms) of the recorded frames."""
+    f = np.zeros(capacity, dtype=np.float32)
+    n = C.c_uint32()
+    _check(lib().mm_batch_profile_end(batch, _fptr(f), C.byref(n)), "mm_batch_profile_end")
+    return f[:n.value]

@@ -58,6 +58,15 @@ __device__ __forceinline__ float fold(float x) {
     return x;
 }
 
+// fold() against a uniform limit, without branches: lim = 1 folds, lim = +inf
+// leaves x as it is. The two tests in sequence equal fold()'s either-or:
+// after x - 2 with x >= 1, x >= -1 holds.
+__device__ __forceinline__ float fold_to(float x, float lim) {
+    x = x >= lim ? x - 2.0f : x;
+    x = x < -lim ? x + 2.0f : x;
+    return x;
+}
+
 struct Float3 {
     float x, y, z;
 };
@@ -89,9 +98,9 @@ __device__ __forceinline__ void store_point(float* pos, uint32_t i, float x, flo
 
 // One timestep of point i: draw keyed by (seed, i, step), add, fold.
 template <int DIM, bool WRAP>
-__device__ __forceinline__ void displace(const PointArgs& a, uint32_t i, float& x, float& y,
-                                         float& z) {
-    const uint4 r = philox4x32_10(a.step, kTagDisplace, i, 0u, a.seed_lo, a.seed_hi);
+__device__ __forceinline__ void displace(const CloudArgs& a, uint32_t step, uint32_t i, float& x,
+                                         float& y, float& z) {
+    const uint4 r = philox4x32_10(step, kTagDisplace, i, 0u, a.seed_lo, a.seed_hi);
     x = x + offset(r.x, a.amp);
     y = y + offset(r.y, a.amp);
     if constexpr (DIM == 3) z = z + offset(r.z, a.amp);
@@ -105,7 +114,7 @@ __device__ __forceinline__ void displace(const PointArgs& a, uint32_t i, float& 
 // Projection to a pixel (row 0 = top). Returns false when culled (behind
 // the near plane or off screen); depth bits are those of clip w (3D) or 0.
 template <int DIM>
-__device__ __forceinline__ bool project(const PointArgs& a, float x, float y, float z,
+__device__ __forceinline__ bool project(const ViewGeom& a, float x, float y, float z,
                                         int32_t& px, int32_t& py, uint32_t& bits) {
     float sx, sy;
     bits = 0u;

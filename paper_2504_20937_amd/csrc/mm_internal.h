@@ -10,19 +10,32 @@ namespace mm {
 
 constexpr uint64_t kEmptyKey = 0xFFFFFFFFFFFFFFFFull;
 
-// Everything a point pass needs, passed by value so the whole struct lands
-// in the kernel-argument segment (uniform, SGPRs).
-struct PointArgs {
+// One point cloud and its displacement draw.
+struct CloudArgs {
     float* pos;         // AoS float2 / float3
-    uint64_t* depth;    // direct splat: width * height keys
     uint32_t n;         // points
-    uint32_t width, height;
-    float half_w, half_h;
-    float fwidth, fheight;
     uint32_t seed_lo, seed_hi;
     uint32_t step;
     float amp;          // a
+    float fold_lim;     // batched kernels: 1 folds each coordinate into [-1, 1)
+                        // after the step, +inf leaves it (plain kernels take the
+                        // fold as a template parameter)
+};
+
+// The screen mapping of one view.
+struct ViewGeom {
+    uint32_t width, height;
+    float half_w, half_h;
+    float fwidth, fheight;
     float m[12];        // rows 0, 1 and 3 of the row-major view-projection
+};
+
+// Direct splat: everything a point pass needs, passed by value so the whole
+// struct lands in the kernel-argument segment (uniform, SGPRs).
+struct PointArgs {
+    CloudArgs c;
+    ViewGeom g;
+    uint64_t* depth;    // width * height keys
 };
 
 struct ResolveArgs {
@@ -32,33 +45,73 @@ struct ResolveArgs {
     uint32_t seed_lo, seed_hi;
 };
 
-// Binned splat, bin pass.
-struct BinArgs {
-    PointArgs p;
+// Binned splat, bin pass side of one view.
+struct BinView {
+    ViewGeom g;
     uint64_t* seg;       // num_wg * P records, P = 256 * points per thread
     uint16_t* table;     // num_wg rows of ntiles + 1 tile start offsets
     uint32_t* active;    // ntiles: stamp of the last frame the tile received points
-    uint32_t* stamp_out; // the frame stamp, for the tile and seam passes
-    uint32_t stamp;
     uint32_t tiles_x, ntiles;
-    uint32_t shift;      // tile side = 1 << shift
 };
 
-// Binned splat, tile and seam passes.
-struct TileArgs {
+// Binned splat, tile and merge side of one view.
+struct TileView {
     const uint64_t* seg;
     const uint16_t* table;
     const uint32_t* active;
-    const uint32_t* stamp_in;
     uint64_t* part;      // ntiles * splits partial key tiles (apron included)
     uint64_t* border;    // footprint 3: ntiles * 4 * side edge keys
     uint64_t* apron;     // footprint 3: ntiles * (4 * side + 4) apron keys
     uint32_t* colour;
     uint32_t width, height;
     uint32_t tiles_x, tiles_y, ntiles;
-    uint32_t num_wg, points_per_wg;
+    uint32_t num_wg;     // bin workgroups (chunks of points) of the view's cloud
     uint32_t splits;     // tile-pass workgroups per tile
+    uint32_t full_clear; // 1: clear every tile not drawn this frame (the frame buffer
+                         // holds no earlier frame); 0: only tiles drawn last frame
     uint32_t seed_lo, seed_hi;
+};
+
+// Binned splat of one cloud into one view.
+struct BinArgs {
+    CloudArgs c;
+    BinView v;
+    uint32_t* stamp_out; // the frame stamp, for the tile, merge and seam passes
+    uint32_t stamp;
+    uint32_t shift;      // tile side = 1 << shift
+};
+
+struct TileArgs {
+    TileView v;
+    const uint32_t* stamp_in;
+    uint32_t points_per_wg;
+};
+
+// Batched binned splat: many clouds, each with one or more views, in one
+// launch per pass. Work items are listed in device tables; a block takes
+// items blockIdx.x, blockIdx.x + gridDim.x, ...
+struct BatchBinArgs {
+    const CloudArgs* clouds;
+    const BinView* views;
+    const uint32_t* first_view;  // clouds + 1 entries: the views of cloud c are
+                                 // first_view[c] .. first_view[c + 1] - 1
+    const uint2* item;           // (cloud, chunk of P points); clouds with views
+    uint32_t items;
+    const uint2* disp_item;      // (cloud, chunk): clouds without views, displaced only
+    uint32_t disp_items;
+    uint32_t* stamp_out;
+    uint32_t stamp;
+    uint32_t shift;
+};
+
+// Tile items are (view, tile << 3 | split); merge and seam items (view, tile << 3).
+// A view of ~0u is a padding item that does nothing.
+struct BatchTileArgs {
+    const TileView* views;
+    const uint2* item;
+    uint32_t items;
+    const uint32_t* stamp_in;
+    uint32_t points_per_wg;
 };
 
 // What a point pass does in one launch.
@@ -86,5 +139,14 @@ Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t n, uint32_t
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits);
 Launch merge_launch(int footprint, int shift, uint32_t ntiles);
 Launch seam_launch(int shift, uint32_t ntiles);
+
+// Batched binned splat. grid_blocks = 0 launches one block per
+// item; otherwise the launch is persistent, each block looping over items.
+Launch batch_bin_launch(int dim, Phase phase, int ppt, uint32_t items, uint32_t max_tiles,
+                        uint32_t grid_blocks);
+Launch batch_displace_launch(int dim, int ppt, uint32_t items, uint32_t grid_blocks);
+Launch batch_tile_launch(int footprint, int shift, uint32_t items, uint32_t grid_blocks);
+Launch batch_merge_launch(int footprint, int shift, uint32_t items, uint32_t grid_blocks);
+Launch batch_seam_launch(int shift, uint32_t items, uint32_t grid_blocks);
 
 }  // namespace mm

@@ -22,31 +22,31 @@ using namespace dev;
 template <int DIM, int FOOT, bool WRAP, int PHASE>
 __global__ __launch_bounds__(256) void point_kernel(PointArgs a) {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (i >= a.n) return;
+    if (i >= a.c.n) return;
     float x, y, z;
-    load_point<DIM>(a.pos, i, x, y, z);
+    load_point<DIM>(a.c.pos, i, x, y, z);
     if constexpr ((PHASE & kDisplace) != 0) {
-        displace<DIM, WRAP>(a, i, x, y, z);
-        store_point<DIM>(a.pos, i, x, y, z);
+        displace<DIM, WRAP>(a.c, a.c.step, i, x, y, z);
+        store_point<DIM>(a.c.pos, i, x, y, z);
     }
     if constexpr ((PHASE & kRender) != 0) {
         int32_t px, py;
         uint32_t bits;
-        if (!project<DIM>(a, x, y, z, px, py, bits)) return;
+        if (!project<DIM>(a.g, x, y, z, px, py, bits)) return;
         const uint64_t key = (static_cast<uint64_t>(bits) << 32) | i;
         if constexpr (FOOT == 1) {
-            uint64_t* slot = a.depth + static_cast<uint64_t>(py) * a.width + px;
+            uint64_t* slot = a.depth + static_cast<uint64_t>(py) * a.g.width + px;
             if (key < *slot) atomic_min_global(slot, key);
         } else {
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy) {
                 const int32_t qy = py + dy;
-                if (qy < 0 || qy >= static_cast<int32_t>(a.height)) continue;
+                if (qy < 0 || qy >= static_cast<int32_t>(a.g.height)) continue;
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int32_t qx = px + dx;
-                    if (qx < 0 || qx >= static_cast<int32_t>(a.width)) continue;
-                    uint64_t* slot = a.depth + static_cast<uint64_t>(qy) * a.width + qx;
+                    if (qx < 0 || qx >= static_cast<int32_t>(a.g.width)) continue;
+                    uint64_t* slot = a.depth + static_cast<uint64_t>(qy) * a.g.width + qx;
                     if (key < *slot) atomic_min_global(slot, key);
                 }
             }
@@ -111,7 +111,7 @@ Launch resolve_launch(uint64_t npix) {
 
 hipError_t launch_point(const PointArgs& a, int dim, int footprint, bool wrap, Phase phase,
                         hipStream_t s) {
-    const Launch l = point_launch(dim, footprint, wrap, phase, a.n);
+    const Launch l = point_launch(dim, footprint, wrap, phase, a.c.n);
     PointArgs copy = a;
     void* args[] = {&copy};
     return hipLaunchKernel(l.func, l.grid, l.block, args, 0, s);

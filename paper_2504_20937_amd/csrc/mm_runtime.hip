@@ -18,16 +18,7 @@
 #include <string>
 #include <vector>
 
-#include "mm.h"
-#include "mm_internal.h"
-
-struct mm_alloc_s {
-    mm_instance inst;
-    void* ptr;
-    size_t bytes;
-    bool owned;
-    uint32_t users;  // views referring to it
-};
+#include "mm_host.h"
 
 namespace {
 
@@ -68,100 +59,18 @@ struct mm_view_s {
     bool profiling = false;
 };
 
-struct mm_instance_s {
-    int device;
-    hipStream_t stream;
-    bool owns_stream;
-    std::set<mm_alloc> allocs;
-    std::set<mm_view> views;
-};
-
 namespace {
 
+using namespace mmh;
+
 thread_local std::string g_last_error;
-
-mm_status fail(mm_status st, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    std::vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return st;
-}
-
-mm_status hip_fail(hipError_t e, const char* what) {
-    return fail(e == hipErrorOutOfMemory ? MM_ERR_OUT_OF_MEMORY : MM_ERR_HIP, "%s failed: %s",
-                what, hipGetErrorString(e));
-}
-
-#define MM_HIP(call)                                                                        \
-    do {                                                                                    \
-        const hipError_t e_ = (call);                                                       \
-        if (e_ != hipSuccess)                                                               \
-            return fail(e_ == hipErrorOutOfMemory ? MM_ERR_OUT_OF_MEMORY : MM_ERR_HIP,       \
-                        "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
-                        __LINE__);                                                          \
-    } while (0)
-
-#define MM_TRY(expr)                       \
-    do {                                   \
-        const mm_status s_ = (expr);       \
-        if (s_ != MM_OK) return s_;        \
-    } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-bool amplitude_ok(float a) {
-    return a == 0.0f || (std::isfinite(a) && a >= 0x1p-64f && a <= 0x1p64f);
-}
-
-uint32_t shift_of(uint32_t side) {
-    return side == 16 ? 4u : side == 32 ? 5u : side == 64 ? 6u : 0u;
-}
-
-void set_camera_rows(mm::PointArgs& a, const float m[16]) {
-    const int rows[3] = {0, 1, 3};
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 4; ++c) a.m[4 * r + c] = m[4 * rows[r] + c];
-}
 
 void fill_point_args(mm_view v) {
     const mm_view_desc& d = v->desc;
     mm::PointArgs& a = v->args;
-    a.pos = static_cast<float*>(v->position->ptr);
+    a.c = cloud_args(v->position->ptr, d.element_count, d.seed, d.amplitude);
+    a.g = view_geom(d.width, d.height, d.view_proj);
     a.depth = v->depth;
-    a.n = static_cast<uint32_t>(d.element_count);
-    a.width = d.width;
-    a.height = d.height;
-    a.half_w = static_cast<float>(d.width / 2u);
-    a.half_h = static_cast<float>(d.height / 2u);
-    a.fwidth = static_cast<float>(d.width);
-    a.fheight = static_cast<float>(d.height);
-    a.seed_lo = static_cast<uint32_t>(d.seed);
-    a.seed_hi = static_cast<uint32_t>(d.seed >> 32);
-    a.amp = d.amplitude;
-    set_camera_rows(a, d.view_proj);
-}
-
-hipKernelNodeParams node_params(const mm::Launch& l, void** args) {
-    hipKernelNodeParams p{};
-    p.func = const_cast<void*>(l.func);
-    p.gridDim = l.grid;
-    p.blockDim = l.block;
-    p.sharedMemBytes = l.shared;
-    p.kernelParams = args;
-    p.extra = nullptr;
-    return p;
 }
 
 bool binned(mm_view v) { return v->tuning.splat == MM_SPLAT_BINNED; }
@@ -263,11 +172,6 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
     return MM_OK;
 }
 
-template <typename T>
-hipError_t alloc_n(T** p, uint64_t n) {
-    return hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
-}
-
 // Allocates the splat scratch buffers of v->tuning, fills the kernel
 // argument blocks and builds the plain frame graph.
 mm_status setup_splat(mm_view v) {
@@ -283,8 +187,8 @@ mm_status setup_splat(mm_view v) {
         if (e == hipSuccess) e = mm::launch_fill(v->depth, npix, mm::kEmptyKey, inst->stream);
         if (e != hipSuccess) return hip_fail(e, "direct splat buffers");
         fill_point_args(v);
-        v->rargs = mm::ResolveArgs{v->depth, v->colour, npix, v->args.seed_lo, v->args.seed_hi};
-        v->nodes.push_back(mm::point_launch(dim, foot, wrap, mm::kDisplaceRender, v->args.n));
+        v->rargs = mm::ResolveArgs{v->depth, v->colour, npix, v->args.c.seed_lo, v->args.c.seed_hi};
+        v->nodes.push_back(mm::point_launch(dim, foot, wrap, mm::kDisplaceRender, v->args.c.n));
         v->nodes.push_back(mm::resolve_launch(npix));
     } else {
         const uint32_t side = v->tuning.tile, shift = shift_of(side);
@@ -310,35 +214,36 @@ mm_status setup_splat(mm_view v) {
         v->stamp = 0;
         fill_point_args(v);
         mm::BinArgs& b = v->bargs;
-        b.p = v->args;
-        b.seg = v->seg;
-        b.table = v->table;
-        b.active = v->active;
+        b.c = v->args.c;
+        b.v.g = v->args.g;
+        b.v.seg = v->seg;
+        b.v.table = v->table;
+        b.v.active = v->active;
+        b.v.tiles_x = v->tiles_x;
+        b.v.ntiles = v->ntiles;
         b.stamp_out = v->active + v->ntiles;
         b.stamp = 0;
-        b.tiles_x = v->tiles_x;
-        b.ntiles = v->ntiles;
         b.shift = shift;
         mm::TileArgs& t = v->targs;
-        t.seg = v->seg;
-        t.table = v->table;
-        t.active = v->active;
+        t.v.seg = v->seg;
+        t.v.table = v->table;
+        t.v.active = v->active;
+        t.v.part = v->part;
+        t.v.border = v->border;
+        t.v.apron = v->apron;
+        t.v.colour = v->colour;
+        t.v.width = d.width;
+        t.v.height = d.height;
+        t.v.tiles_x = v->tiles_x;
+        t.v.tiles_y = v->tiles_y;
+        t.v.ntiles = v->ntiles;
+        t.v.num_wg = v->num_wg;
+        t.v.splits = v->tuning.splits;
+        t.v.seed_lo = v->args.c.seed_lo;
+        t.v.seed_hi = v->args.c.seed_hi;
         t.stamp_in = v->active + v->ntiles;
-        t.part = v->part;
-        t.border = v->border;
-        t.apron = v->apron;
-        t.colour = v->colour;
-        t.width = d.width;
-        t.height = d.height;
-        t.tiles_x = v->tiles_x;
-        t.tiles_y = v->tiles_y;
-        t.ntiles = v->ntiles;
-        t.num_wg = v->num_wg;
         t.points_per_wg = static_cast<uint32_t>(P);
-        t.splits = v->tuning.splits;
-        t.seed_lo = v->args.seed_lo;
-        t.seed_hi = v->args.seed_hi;
-        v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, v->args.n, v->ntiles));
+        v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, v->args.c.n, v->ntiles));
         v->nodes.push_back(mm::tile_launch(foot, static_cast<int>(shift), v->ntiles, v->tuning.splits));
         v->nodes.push_back(mm::merge_launch(foot, static_cast<int>(shift), v->ntiles));
         if (foot == 3) v->nodes.push_back(mm::seam_launch(static_cast<int>(shift), v->ntiles));
@@ -362,42 +267,14 @@ void destroy_view_resources(mm_view v) {
 }
 
 mm_status validate_desc(mm_instance inst, const mm_view_desc* d) {
-    if (!d->position) return fail(MM_ERR_INVALID_ARG, "view: position alloc is null");
-    if (d->position->inst != inst)
-        return fail(MM_ERR_INVALID_ARG, "view: position alloc belongs to another instance");
-    if (d->format != MM_FLOAT2 && d->format != MM_FLOAT3)
-        return fail(MM_ERR_INVALID_ARG, "view: format %d is not MM_FLOAT2/MM_FLOAT3",
-                    (int)d->format);
     if (d->domain != MM_DOMAIN_2D && d->domain != MM_DOMAIN_3D)
         return fail(MM_ERR_INVALID_ARG, "view: domain %d is not 2D/3D", (int)d->domain);
-    if ((int)d->format != (int)d->domain)
-        return fail(MM_ERR_UNSUPPORTED, "view: format float%d with a %dD domain",
-                    (int)d->format, (int)d->domain);
-    if (d->element_count < 1 || d->element_count > 0xFFFFFFFFull)
-        return fail(MM_ERR_INVALID_ARG, "view: element_count %llu outside [1, 2^32-1]",
-                    (unsigned long long)d->element_count);
-    const uint64_t stride = 4ull * (uint64_t)d->format;
-    if (d->element_count > d->position->bytes / stride)
-        return fail(MM_ERR_INVALID_ARG, "view: %llu points of %llu B exceed the %zu-byte alloc",
-                    (unsigned long long)d->element_count, (unsigned long long)stride,
-                    d->position->bytes);
-    if (d->width < 2 || d->height < 2 || d->width > 16384 || d->height > 16384 ||
-        (d->width & 1u) || (d->height & 1u))
-        return fail(MM_ERR_INVALID_ARG, "view: screen %ux%u must be even and in [2, 16384]",
-                    d->width, d->height);
+    const mm_cloud_desc c{d->position, d->element_count, d->format, d->seed, d->amplitude, d->wrap};
+    MM_TRY(validate_cloud(inst, c, d->domain, "view"));
+    MM_TRY(validate_screen(d->width, d->height, "view"));
     if (d->footprint != 1 && d->footprint != 3)
         return fail(MM_ERR_INVALID_ARG, "view: footprint %u is not 1 or 3", d->footprint);
-    if (!amplitude_ok(d->amplitude))
-        return fail(MM_ERR_INVALID_ARG, "view: amplitude %g outside {0} U [2^-64, 2^64]",
-                    (double)d->amplitude);
-    if (d->wrap != 0 && d->wrap != 1)
-        return fail(MM_ERR_INVALID_ARG, "view: wrap must be 0 or 1");
-    if (d->wrap && d->amplitude > 1.0f)
-        return fail(MM_ERR_INVALID_ARG, "view: wrap needs amplitude <= 1");
-    if (d->domain == MM_DOMAIN_3D)
-        for (int k = 0; k < 16; ++k)
-            if (!std::isfinite(d->view_proj[k]))
-                return fail(MM_ERR_INVALID_ARG, "view: view_proj[%d] is not finite", k);
+    if (d->domain == MM_DOMAIN_3D) MM_TRY(validate_camera(d->view_proj, "view"));
     return MM_OK;
 }
 
@@ -413,6 +290,63 @@ mm_status next_stamp(mm_view v) {
 }
 
 }  // namespace
+
+namespace mmh {
+
+mm_status fail(mm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+mm_status validate_cloud(mm_instance inst, const mm_cloud_desc& d, mm_domain domain,
+                         const char* what) {
+    if (!d.position) return fail(MM_ERR_INVALID_ARG, "%s: position alloc is null", what);
+    if (inst->allocs.count(d.position) == 0)
+        return fail(MM_ERR_INVALID_ARG, "%s: position is not an alloc of this instance", what);
+    if (d.format != MM_FLOAT2 && d.format != MM_FLOAT3)
+        return fail(MM_ERR_INVALID_ARG, "%s: format %d is not MM_FLOAT2/MM_FLOAT3", what,
+                    (int)d.format);
+    if ((int)d.format != (int)domain)
+        return fail(MM_ERR_UNSUPPORTED, "%s: format float%d with a %dD domain", what,
+                    (int)d.format, (int)domain);
+    if (d.element_count < 1 || d.element_count > 0xFFFFFFFFull)
+        return fail(MM_ERR_INVALID_ARG, "%s: element_count %llu outside [1, 2^32-1]", what,
+                    (unsigned long long)d.element_count);
+    const uint64_t stride = 4ull * (uint64_t)d.format;
+    if (d.element_count > d.position->bytes / stride)
+        return fail(MM_ERR_INVALID_ARG, "%s: %llu points of %llu B exceed the %zu-byte alloc",
+                    what, (unsigned long long)d.element_count, (unsigned long long)stride,
+                    d.position->bytes);
+    if (!amplitude_ok(d.amplitude))
+        return fail(MM_ERR_INVALID_ARG, "%s: amplitude %g outside {0} U [2^-64, 2^64]", what,
+                    (double)d.amplitude);
+    if (d.wrap != 0 && d.wrap != 1) return fail(MM_ERR_INVALID_ARG, "%s: wrap must be 0 or 1", what);
+    if (d.wrap && d.amplitude > 1.0f)
+        return fail(MM_ERR_INVALID_ARG, "%s: wrap needs amplitude <= 1", what);
+    return MM_OK;
+}
+
+mm_status validate_screen(uint32_t width, uint32_t height, const char* what) {
+    if (width < 2 || height < 2 || width > 16384 || height > 16384 || (width & 1u) ||
+        (height & 1u))
+        return fail(MM_ERR_INVALID_ARG, "%s: screen %ux%u must be even and in [2, 16384]", what,
+                    width, height);
+    return MM_OK;
+}
+
+mm_status validate_camera(const float m[16], const char* what) {
+    for (int k = 0; k < 16; ++k)
+        if (!std::isfinite(m[k]))
+            return fail(MM_ERR_INVALID_ARG, "%s: view_proj[%d] is not finite", what, k);
+    return MM_OK;
+}
+
+}  // namespace mmh
 
 extern "C" {
 
@@ -447,7 +381,7 @@ mm_status mm_create_instance(const mm_instance_desc* desc, mm_instance* out) {
         MM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         owns = true;
     }
-    mm_instance inst = new (std::nothrow) mm_instance_s{desc->device, s, owns, {}, {}};
+    mm_instance inst = new (std::nothrow) mm_instance_s{desc->device, s, owns, {}, {}, {}, {}};
     if (!inst) {
         if (owns) (void)hipStreamDestroy(s);
         return fail(MM_ERR_OUT_OF_MEMORY, "create_instance: host allocation");
@@ -469,6 +403,8 @@ mm_status mm_destroy_instance(mm_instance inst) {
     if (!inst) return fail(MM_ERR_INVALID_ARG, "destroy_instance: null instance");
     DeviceGuard guard(inst->device);
     MM_HIP(hipStreamSynchronize(inst->stream));
+    std::vector<mm_batch> batches(inst->batches.begin(), inst->batches.end());
+    for (mm_batch b : batches) mm_destroy_batch(b);
     std::vector<mm_view> views(inst->views.begin(), inst->views.end());
     for (mm_view v : views) mm_destroy_view(v);
     for (mm_alloc a : inst->allocs) {
@@ -598,6 +534,54 @@ mm_status mm_set_tuning(mm_view v, const mm_tuning* req) {
     return st;
 }
 
+mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
+    if (!v || !out) return fail(MM_ERR_INVALID_ARG, "autotune: null argument");
+    if (frames < 1 || frames > 1000) return fail(MM_ERR_INVALID_ARG, "autotune: frames %u outside [1, 1000]", frames);
+    mm_instance inst = v->inst;
+    DeviceGuard guard(inst->device);
+    MM_HIP(hipStreamSynchronize(inst->stream));
+    const mm_view_desc& d = v->desc;
+    char key[256];
+    std::snprintf(key, sizeof key, "view:%s:d%d:n%llu:%ux%u:f%u", device_arch(inst->device).c_str(),
+                  (int)d.domain, (unsigned long long)d.element_count, d.width, d.height, d.footprint);
+    uint32_t cached[4];
+    if (tune_cache_lookup(key, cached)) {
+        const mm_tuning t{cached[0], cached[1], cached[2], cached[3]};
+        if (mm_set_tuning(v, &t) == MM_OK) return mm_get_tuning(v, out);
+    }
+    const size_t bytes = static_cast<size_t>(d.element_count) * 4u * static_cast<size_t>(d.format);
+    void* saved = nullptr;
+    MM_HIP(hipMalloc(&saved, bytes));
+    hipError_t e = hipMemcpyAsync(saved, v->position->ptr, bytes, hipMemcpyDeviceToDevice, inst->stream);
+    std::vector<mm_tuning> cands = {{MM_SPLAT_DIRECT, 0, 0, 0}};
+    for (uint32_t tile : {16u, 32u, 64u})
+        for (uint32_t ppt : {8u, 16u})
+            for (uint32_t splits : {1u, 2u, 4u}) cands.push_back({MM_SPLAT_BINNED, tile, ppt, splits});
+    mm_tuning best{};
+    float best_ms = 0.0f;
+    for (const mm_tuning& c : cands) {
+        if (e != hipSuccess) break;
+        mm_tuning r{};
+        if (resolve_tuning(d, c, r) != MM_OK || mm_set_tuning(v, &c) != MM_OK) continue;
+        const float ms = time_frames(inst->stream, frames, [&] { return mm_step_render(v, 0); });
+        if (ms > 0.0f && (best_ms == 0.0f || ms < best_ms)) {
+            best_ms = ms;
+            best = r;
+        }
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(v->position->ptr, saved, bytes, hipMemcpyDeviceToDevice, inst->stream);
+    const hipError_t se = hipStreamSynchronize(inst->stream);
+    (void)hipFree(saved);
+    if (e != hipSuccess) return hip_fail(e, "autotune: saving or restoring positions");
+    if (se != hipSuccess) return hip_fail(se, "autotune: synchronising");
+    if (best_ms == 0.0f) return fail(MM_ERR_HIP, "autotune: no candidate ran");
+    MM_TRY(mm_set_tuning(v, &best));
+    const uint32_t vals[4] = {best.splat, best.tile, best.points_per_thread, best.splits};
+    tune_cache_store(key, vals);
+    return mm_get_tuning(v, out);
+}
+
 mm_status mm_get_tuning(mm_view v, mm_tuning* out) {
     if (!v || !out) return fail(MM_ERR_INVALID_ARG, "get_tuning: null argument");
     *out = v->tuning;
@@ -609,8 +593,8 @@ mm_status mm_set_camera(mm_view v, const float m[16]) {
     for (int k = 0; k < 16; ++k)
         if (!std::isfinite(m[k])) return fail(MM_ERR_INVALID_ARG, "set_camera: m[%d] not finite", k);
     std::memcpy(v->desc.view_proj, m, sizeof(float) * 16);
-    set_camera_rows(v->args, m);
-    set_camera_rows(v->bargs.p, m);
+    set_camera_rows(v->args.g, m);
+    set_camera_rows(v->bargs.v.g, m);
     return MM_OK;
 }
 
@@ -624,7 +608,7 @@ mm_status mm_step(mm_view v, uint32_t step) {
     MM_TRY(require_ready(v, "step"));
     DeviceGuard guard(v->inst->device);
     mm::PointArgs a = v->args;
-    a.step = step;
+    a.c.step = step;
     MM_HIP(mm::launch_point(a, static_cast<int>(v->desc.domain), static_cast<int>(v->desc.footprint),
                             v->desc.wrap != 0, mm::kDisplace, v->inst->stream));
     return MM_OK;
@@ -642,7 +626,7 @@ mm_status mm_render(mm_view v) {
     }
     MM_TRY(next_stamp(v));
     const mm::Launch b = mm::bin_launch(dim, v->desc.wrap != 0, mm::kRender,
-                                        static_cast<int>(v->tuning.points_per_thread), v->args.n,
+                                        static_cast<int>(v->tuning.points_per_thread), v->args.c.n,
                                         v->ntiles);
     void* bargs[] = {&v->bargs};
     MM_HIP(hipLaunchKernel(b.func, b.grid, b.block, bargs, b.shared, s));
@@ -660,10 +644,10 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
     void* first_arg;
     if (binned(v)) {
         MM_TRY(next_stamp(v));
-        v->bargs.p.step = step;
+        v->bargs.c.step = step;
         first_arg = &v->bargs;
     } else {
-        v->args.step = step;
+        v->args.c.step = step;
         first_arg = &v->args;
     }
     void* args[] = {first_arg};

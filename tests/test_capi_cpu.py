@@ -86,3 +86,45 @@ def test_header_struct_layout_compiles_to_the_same_offsets(tmp_path):
                     str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     assert out == ["40", "48", "52", "56", "120", str(C.sizeof(mm.mm_instance_desc))]
+
+
+def test_batch_calls_reject_null_arguments_without_a_device():
+    L = mm.lib()
+    assert L.mm_create_batch(None, None, None) == mm.MM_ERR_INVALID_ARG
+    for name in ["mm_destroy_batch", "mm_batch_render"]:
+        assert getattr(L, name)(None) == mm.MM_ERR_INVALID_ARG, name
+    assert L.mm_batch_step_render(None, 0) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_batch_set_camera(None, 0, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_batch_read_frame(None, 0, None, 0) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_batch_set_tuning(None, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_batch_profile_begin(None, 4) == mm.MM_ERR_INVALID_ARG
+
+
+def _c_layout(tmp_path, exprs):
+    src = tmp_path / "layout2.c"
+    fmt = " ".join(["%zu"] * len(exprs))
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "mm.h"\n'
+                   'int main(void){printf("' + fmt + '\\n", ' + ", ".join(exprs) + ");return 0;}\n")
+    exe = tmp_path / "layout2"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    return [int(x) for x in out]
+
+
+def test_batch_struct_layouts_match_the_header(tmp_path):
+    structs = {
+        "mm_cloud_desc": mm.mm_cloud_desc,
+        "mm_batch_view_desc": mm.mm_batch_view_desc,
+        "mm_batch_desc": mm.mm_batch_desc,
+        "mm_batch_tuning": mm.mm_batch_tuning,
+    }
+    exprs, expect = [], []
+    for cname, py in structs.items():
+        for fname, _ in py._fields_:
+            exprs.append(f"offsetof({cname}, {fname})")
+            expect.append(getattr(py, fname).offset)
+        exprs.append(f"sizeof({cname})")
+        expect.append(C.sizeof(py))
+    assert _c_layout(tmp_path, exprs) == expect
