@@ -217,6 +217,171 @@ def bench_batched(args) -> dict:
     }
 
 
+SERVED_SCREENS = [(1280, 720), (1920, 1080), (3840, 2160)]
+
+
+def bench_served(args) -> dict:
+    """Poisson arrivals of displace+render requests from 256 sessions on the 64
+    clouds of the batched workload; each session has one screen (720p, 1080p
+    or 4K); the server batches them continuously. Reports latency from
+    submission to completion and the throughput, at the given rate and with
+    every request submitted at once (saturation)."""
+    import torch
+
+    import paper_2504_20937_amd as mm
+    import synth
+
+    specs, pts = batch_workload()
+    stream = torch.cuda.current_stream()
+    inst = mm.mm_create_instance(0, stream.cuda_stream)
+    devs, allocs = [], []
+    for sp, p in zip(specs, pts):
+        d = torch.from_numpy(p).cuda()
+        devs.append(d)
+        allocs.append(mm.mm_alloc_wrap(inst, d.data_ptr(), d.numel() * 4))
+    sizes = [p.shape[0] for p in pts]
+    del pts
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    n_sessions = 256
+    screens = [SERVED_SCREENS[int(rng.integers(0, 3))] for _ in range(n_sessions)]
+
+    def run(rate, count, budget, seed):
+        srv = mm.mm_create_server(inst, budget, args.streams, args.max_batch, 3, 1,
+                                  args.tile, args.ppt, args.splits, args.grid)
+        for j, sp in enumerate(specs):
+            mm.mm_server_add_cloud(srv, mm.make_cloud_desc(allocs[j], sizes[j], 3, sp.seed, 0.001))
+        r = np.random.default_rng(seed)
+        sess = r.integers(0, n_sessions, count)
+        cl = r.integers(0, len(specs), count)
+        deg = r.uniform(0.0, 360.0, count)
+        cams = [synth.orbit_camera(0, screens[s][0], screens[s][1], start_deg=float(a))
+                for s, a in zip(sess, deg)]
+        arrivals = (synth.poisson_arrivals(rate, count, seed) if np.isfinite(rate)
+                    else np.zeros(count))
+        ids = []
+        t0 = time.perf_counter()
+        for k in range(count):
+            while time.perf_counter() - t0 < arrivals[k]:
+                pass
+            w, h = screens[sess[k]]
+            ids.append(mm.mm_server_submit(srv, int(sess[k]), int(cl[k]), cams[k], w, h))
+        lat = np.array([mm.mm_server_wait(srv, i) for i in ids])
+        t1 = time.perf_counter()
+        st = mm.mm_server_stats_get(srv)
+        mm.mm_destroy_server(srv)
+        pts_done = float(sum(sizes[c] for c in cl))
+        px_done = float(sum(screens[s][0] * screens[s][1] for s in sess))
+        return {"rate_per_s": None if not np.isfinite(rate) else rate, "requests": count,
+                "budget_bytes": budget, "wall_s": t1 - t0,
+                "frames_per_s": count / (t1 - t0), "Gpoints_per_s": pts_done / (t1 - t0) / 1e9,
+                "Gpixels_per_s": px_done / (t1 - t0) / 1e9,
+                "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+                "launches": st["launches"], "mean_batch": count / max(1, st["launches"]),
+                "evictions": st["evictions"], "admissions": st["admissions"]}
+
+    count = args.requests
+    print(f"bench served: 256 sessions, {len(specs)} clouds, {count} requests per run",
+          file=sys.stderr, flush=True)
+    runs = [run(args.rate, count, 64 << 30, 1), run(args.rate, count, 1 << 30, 2)]
+    for rate in (4 * args.rate, 16 * args.rate, float("inf")):
+        runs.append(run(rate, count, 64 << 30, 3))
+        print(f"  rate {rate}: {runs[-1]['frames_per_s']:.0f} frames/s", file=sys.stderr, flush=True)
+    for a in allocs:
+        mm.mm_free(a)
+    mm.mm_destroy_instance(inst)
+    main_run = runs[0]
+    return {
+        "metric": "served displace+render: p50/p99 request latency and frames/s, 256 sessions, "
+                  "Poisson arrivals, 64 clouds (2^12..2^22 pts), 720p/1080p/4K",
+        "value": main_run["frames_per_s"], "unit": "frames/s",
+        "n_gpus": 1, "steps": count, "warmup": 0,
+        "ms_per_step": main_run["wall_s"] / count * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"served-256-sessions-poisson-{args.rate:g}-per-s",
+                   "streams": args.streams, "max_batch": args.max_batch},
+        "p50_latency_ms": main_run["p50_latency_ms"],
+        "p99_latency_ms": main_run["p99_latency_ms"],
+        "runs": runs,
+    }
+
+
+def bench_hostcopy(args) -> dict:
+    """The comparison the paper draws: per frame the device displaces the
+    cloud, the positions are copied to host memory, and the host renders
+    them on all its cores. Beside it, the device path on the same workload."""
+    import torch
+
+    import paper_2504_20937_amd as mm
+    from paper_2504_20937_amd import hostcopy
+    import synth
+
+    n, w, h = 1 << args.log2n, args.width, args.height
+    K = max(1, args.hostcopy_frames)
+    pts = synth.uniform_cube(n, 0)
+    dev = torch.from_numpy(pts).cuda()
+    del pts
+    host = torch.empty((n, 3), dtype=torch.float32, pin_memory=True)
+    frame = np.empty((h, w), dtype=np.uint32)
+    stream = torch.cuda.current_stream()
+    inst = mm.mm_create_instance(0, stream.cuda_stream)
+    alloc = mm.mm_alloc_wrap(inst, dev.data_ptr(), dev.numel() * 4)
+    view = mm.mm_create_view(inst, mm.make_view_desc(alloc, n, 3, w, h, 1, 0, 0.001, False,
+                                                     synth.orbit_camera(0, w, h)))
+    threads = hostcopy.max_threads()
+    hostcopy.render(np.zeros((1, 3), np.float32), 0, synth.orbit_camera(0, w, h), w, h)  # warm
+    t_disp = t_copy = t_render = 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(K):
+        a = time.perf_counter()
+        mm.mm_step(view, f)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        host.copy_(dev)            # device -> pinned host, 12 B per point
+        c = time.perf_counter()
+        hostcopy.render(host.numpy(), 0, synth.orbit_camera(f, w, h), w, h, 1, threads, frame)
+        d = time.perf_counter()
+        t_disp += b - a
+        t_copy += c - b
+        t_render += d - c
+    elapsed = time.perf_counter() - t0
+    # the device path on the same workload, for the ratio
+    G = 200
+    for f in range(20):
+        mm.mm_set_camera(view, synth.orbit_camera(f, w, h))
+        mm.mm_step_render(view, K + f)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for f in range(G):
+        mm.mm_set_camera(view, synth.orbit_camera(f, w, h))
+        mm.mm_step_render(view, K + 20 + f)
+    torch.cuda.synchronize()
+    g_elapsed = time.perf_counter() - g0
+    mm.mm_destroy_view(view)
+    mm.mm_free(alloc)
+    mm.mm_destroy_instance(inst)
+    fps = K / elapsed
+    gpu_fps = G / g_elapsed
+    return {
+        "metric": "host-copy path (device displace, copy to host, render on all host cores) "
+                  "vs device path, 2^24 pts 1080p",
+        "value": fps, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": 0,
+        "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"3d-uniform-2^{args.log2n}pts-{w}x{h}-orbit-1deg-hostcopy",
+                   "host_threads": threads, "cpus": len(os.sched_getaffinity(0))},
+        "displace_ms": t_disp / K * 1e3, "copy_ms": t_copy / K * 1e3,
+        "render_ms": t_render / K * 1e3,
+        "pcie_GBps": 12.0 * n * K / t_copy / 1e9,
+        "host_memory_bytes": 12 * n + 4 * w * h + 8 * w * h * threads,
+        "device_path_frames_per_s": gpu_fps,
+        "device_over_hostcopy": gpu_fps / fps,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,9 +398,17 @@ def main() -> int:
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0, help="batched: persistent grid blocks")
     ap.add_argument("--autotune", action="store_true", help="time the shapes, keep the fastest")
-    ap.add_argument("--workload", choices=["frame", "batched"], default="frame",
+    ap.add_argument("--hostcopy-frames", type=int, default=10, help="hostcopy: frames timed")
+    ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy"],
+                    default="frame",
                     help="frame: the 2^24-point 1080p frame (default); batched: 64 clouds "
-                         "with 1-4 views each in one launch per pass")
+                         "with 1-4 views each in one launch per pass; served: Poisson "
+                         "requests from 256 sessions through the server; hostcopy: device "
+                         "displace, copy to host, render on the host cores")
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: requests per second")
+    ap.add_argument("--requests", type=int, default=4000, help="served: requests per run")
+    ap.add_argument("--streams", type=int, default=2, help="served: streams")
+    ap.add_argument("--max-batch", type=int, default=256, help="served: requests per launch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 10 plain device copies of BYTES (for scaling the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -265,6 +438,12 @@ def main() -> int:
         return 0
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
+        return 0
+    if args.workload == "served":
+        print(json.dumps(bench_served(args)), flush=True)
+        return 0
+    if args.workload == "hostcopy":
+        print(json.dumps(bench_hostcopy(args)), flush=True)
         return 0
     n, w, h = 1 << args.log2n, args.width, args.height
     K, W = args.steps, args.warmup

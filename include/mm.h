@@ -296,6 +296,82 @@ mm_status mm_batch_autotune(mm_batch batch, uint32_t frames, mm_batch_tuning* ou
 mm_status mm_batch_profile_begin(mm_batch batch, uint32_t capacity);
 mm_status mm_batch_profile_end(mm_batch batch, float* frame_ms, uint32_t* count);
 
+/* ------------------------------------------------------------------ server
+ * Served rendering (the remote-rendering direction the paper names as
+ * future work, section "Conclusions and limitations"): clients submit
+ * requests (session, cloud, camera, screen); a scheduler thread packs the
+ * pending requests of many sessions into batched launches (continuous
+ * batching over a few streams) and admits a session only while its frame
+ * buffer fits the memory budget.
+ *
+ * Order and results: every cloud added to the server has a step counter.
+ * Requests on one cloud are served in submission order, and the k-th
+ * request on a cloud (k from 0) displaces the cloud with step k and then
+ * renders it. Its frame therefore equals the plain frame of that cloud
+ * after steps 0..k, whatever else is queued or in flight.
+ *
+ * A session's frame buffer is its RGBA8 frame (4 B per pixel) plus the
+ * per-tile scratch of the depth test; its screen is fixed by its first
+ * request. It is held from admission until the session is closed, or until
+ * the scheduler evicts it (least recently used first) while it is idle and
+ * the budget is needed by a waiting session; an evicted session's frame is
+ * lost. The server's calls may come from any thread. */
+typedef struct {
+    uint64_t fb_budget_bytes;   /* frame-buffer bytes the admitted sessions may hold */
+    uint32_t streams;           /* launches in flight at once: 1..4 */
+    uint32_t max_batch;         /* requests per launch: 1..4096 */
+    mm_domain domain;           /* of every cloud */
+    uint32_t footprint;         /* 1 or 3 */
+    mm_batch_tuning tuning;     /* tile (0: 64), points_per_thread (0: 16), splits, grid_blocks */
+} mm_server_desc;
+
+typedef struct {
+    uint64_t submitted, completed, launches;
+    uint64_t admitted_sessions;  /* sessions holding a frame buffer now */
+    uint64_t admissions, evictions;
+    uint64_t fb_bytes_in_use;    /* held by admitted sessions and kept for reuse */
+    uint64_t queued;             /* submitted, not yet launched */
+} mm_server_stats;
+
+/* Creates the server and starts its scheduler thread. Its streams are
+ * created by the server (default priority, non-blocking). */
+mm_status mm_create_server(mm_instance inst, const mm_server_desc* desc, mm_server* out);
+
+/* Stops the scheduler after the launches in flight; queued requests are
+ * dropped. Frees every buffer of the server. */
+mm_status mm_destroy_server(mm_server server);
+
+/* Registers a cloud (the server refers to its alloc until destroyed);
+ * *cloud_id receives its index (0, 1, ...). Its step counter starts at 0. */
+mm_status mm_server_add_cloud(mm_server server, const mm_cloud_desc* cloud, uint32_t* cloud_id);
+
+/* Queues one displace+render request and returns at once. dev_out: NULL
+ * renders into the session's frame; else the device address of width *
+ * height uint32 owned by the caller, which receives the frame instead.
+ * MM_ERR_BUDGET if the session's frame buffer alone exceeds the budget;
+ * MM_ERR_INVALID_ARG for a screen other than the session's. */
+mm_status mm_server_submit(mm_server server, uint32_t session, uint32_t cloud,
+                           const float view_proj[16], uint32_t width, uint32_t height,
+                           uint32_t* dev_out, uint64_t* request_id);
+
+/* *done = 1 once the request's frame is complete on the device, with
+ * *latency_s the time from submission to completion (may be NULL). */
+mm_status mm_server_poll(mm_server server, uint64_t request_id, int32_t* done,
+                         double* latency_s);
+
+/* Blocks until the request is complete (or the server stops: MM_ERR_NOT_READY). */
+mm_status mm_server_wait(mm_server server, uint64_t request_id, double* latency_s);
+
+/* Copies the session's frame (its last completed request drawn into it) to
+ * host memory. MM_ERR_NOT_READY if the session holds no frame buffer. */
+mm_status mm_server_read_frame(mm_server server, uint32_t session, void* host_rgba,
+                               size_t bytes);
+
+/* The session's frame buffer is released once its queued requests are done. */
+mm_status mm_server_close_session(mm_server server, uint32_t session);
+
+mm_status mm_server_stats_get(mm_server server, mm_server_stats* out);
+
 /* ------------------------------------------------------------ diagnostics */
 const char* mm_status_string(mm_status status);
 const char* mm_last_error(void);

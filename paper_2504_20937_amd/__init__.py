@@ -106,6 +106,23 @@ class mm_batch_tuning(C.Structure):
                 ("grid_blocks", C.c_uint32)]
 
 
+class mm_server_desc(C.Structure):
+    _fields_ = [
+        ("fb_budget_bytes", C.c_uint64),
+        ("streams", C.c_uint32),
+        ("max_batch", C.c_uint32),
+        ("domain", C.c_int),
+        ("footprint", C.c_uint32),
+        ("tuning", mm_batch_tuning),
+    ]
+
+
+class mm_server_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "launches",
+                                           "admitted_sessions", "admissions", "evictions",
+                                           "fb_bytes_in_use", "queued")]
+
+
 _lib = None
 _status = C.c_int32
 _vp = C.c_void_p
@@ -137,6 +154,16 @@ def _declare(L):
                             C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
         "mm_autotune": ([_vp, C.c_uint32, C.POINTER(mm_tuning)], _status),
         "mm_batch_autotune": ([_vp, C.c_uint32, C.POINTER(mm_batch_tuning)], _status),
+        "mm_create_server": ([_vp, C.POINTER(mm_server_desc), C.POINTER(_vp)], _status),
+        "mm_destroy_server": ([_vp], _status),
+        "mm_server_add_cloud": ([_vp, C.POINTER(mm_cloud_desc), C.POINTER(C.c_uint32)], _status),
+        "mm_server_submit": ([_vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_float), C.c_uint32,
+                              C.c_uint32, _vp, C.POINTER(C.c_uint64)], _status),
+        "mm_server_poll": ([_vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_double)], _status),
+        "mm_server_wait": ([_vp, C.c_uint64, C.POINTER(C.c_double)], _status),
+        "mm_server_read_frame": ([_vp, C.c_uint32, _vp, C.c_size_t], _status),
+        "mm_server_close_session": ([_vp, C.c_uint32], _status),
+        "mm_server_stats_get": ([_vp, C.POINTER(mm_server_stats)], _status),
         "mm_create_batch": ([_vp, C.POINTER(mm_batch_desc), C.POINTER(_vp)], _status),
         "mm_destroy_batch": ([_vp], _status),
         "mm_batch_set_camera": ([_vp, C.c_uint32, C.POINTER(C.c_float)], _status),
@@ -428,3 +455,68 @@ def mm_batch_profile_end(batch: int, capacity: int) -> np.ndarray:
     n = C.c_uint32()
     _check(lib().mm_batch_profile_end(batch, _fptr(f), C.byref(n)), "mm_batch_profile_end")
     return f[:n.value]
+
+
+# -------------------------------------------------------------------- server
+def mm_create_server(inst: int, fb_budget_bytes: int, streams: int = 2, max_batch: int = 256,
+                     dim: int = 3, footprint: int = 1, tile: int = 0, points_per_thread: int = 0,
+                     splits: int = 0, grid_blocks: int = 0) -> int:
+    d = mm_server_desc()
+    d.fb_budget_bytes = fb_budget_bytes
+    d.streams, d.max_batch = streams, max_batch
+    d.domain = MM_DOMAIN_2D if dim == 2 else MM_DOMAIN_3D
+    d.footprint = footprint
+    d.tuning = mm_batch_tuning(tile, points_per_thread, splits, grid_blocks)
+    out = _vp()
+    _check(lib().mm_create_server(inst, C.byref(d), C.byref(out)), "mm_create_server")
+    return out.value
+
+
+def mm_destroy_server(server: int) -> None:
+    _check(lib().mm_destroy_server(server), "mm_destroy_server")
+
+
+def mm_server_add_cloud(server: int, cloud: mm_cloud_desc) -> int:
+    out = C.c_uint32()
+    _check(lib().mm_server_add_cloud(server, C.byref(cloud), C.byref(out)), "mm_server_add_cloud")
+    return out.value
+
+
+def mm_server_submit(server: int, session: int, cloud: int, view_proj, width: int, height: int,
+                     dev_out: int | None = None) -> int:
+    m = np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(16))
+    out = C.c_uint64()
+    _check(lib().mm_server_submit(server, session, cloud, _fptr(m), width, height, dev_out or None,
+                                  C.byref(out)), "mm_server_submit")
+    return out.value
+
+
+def mm_server_poll(server: int, request_id: int) -> tuple[bool, float | None]:
+    done = C.c_int32()
+    lat = C.c_double()
+    _check(lib().mm_server_poll(server, request_id, C.byref(done), C.byref(lat)), "mm_server_poll")
+    return bool(done.value), (lat.value if done.value else None)
+
+
+def mm_server_wait(server: int, request_id: int) -> float:
+    """Blocks until the request is complete; returns its latency in seconds."""
+    lat = C.c_double()
+    _check(lib().mm_server_wait(server, request_id, C.byref(lat)), "mm_server_wait")
+    return lat.value
+
+
+def mm_server_read_frame(server: int, session: int, width: int, height: int) -> np.ndarray:
+    out = np.empty((height, width), dtype=np.uint32)
+    _check(lib().mm_server_read_frame(server, session, out.ctypes.data, out.nbytes),
+           "mm_server_read_frame")
+    return out
+
+
+def mm_server_close_session(server: int, session: int) -> None:
+    _check(lib().mm_server_close_session(server, session), "mm_server_close_session")
+
+
+def mm_server_stats_get(server: int) -> dict:
+    st = mm_server_stats()
+    _check(lib().mm_server_stats_get(server, C.byref(st)), "mm_server_stats_get")
+    return {n: getattr(st, n) for n, _ in mm_server_stats._fields_}

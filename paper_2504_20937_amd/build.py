@@ -12,6 +12,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmm.so")
+HOSTCOPY = os.path.join(PKG, "hostcopy")
+HOSTCOPY_LIB = os.path.join(PKG, "libmm_hostcopy.so")
 ARCH = "gfx950"
 HIPFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -57,7 +59,23 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("linking libmm.so failed")
     os.replace(tmp, LIB)
+    build_hostcopy()
     return LIB
+
+
+def build_hostcopy() -> str:
+    """The host-copy comparison renderer: plain C with OpenMP, binary32 with
+    no contraction (its frames must equal the device path's)."""
+    tmp = HOSTCOPY_LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-I", HOSTCOPY, os.path.join(HOSTCOPY, "hostcopy.c"),
+           "-o", tmp, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("building libmm_hostcopy.so failed")
+    os.replace(tmp, HOSTCOPY_LIB)
+    return HOSTCOPY_LIB
 
 
 if __name__ == "__main__":

@@ -104,21 +104,17 @@ __device__ void block_exclusive_scan(uint32_t* h, uint32_t count, uint32_t* wave
     if (tid == 0) h[count] = total;
 }
 
-// The PPT points per thread of chunk [base, base + P). Points past n read as 0.
+// The PPT points per thread of chunk [base, base + P). Lanes past the end of
+// the cloud load its last point instead (their values are never used): no
+// branch around the loads, so all PPT loads are in flight together.
 template <int DIM, int PPT>
 __device__ __forceinline__ void load_chunk(const CloudArgs& c, uint32_t base, float (&xs)[PPT],
                                            float (&ys)[PPT], float (&zs)[PPT]) {
     const uint32_t tid = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const uint32_t i = base + k * 256u + tid;
-        if (i < c.n) {
-            load_point<DIM>(c.pos, i, xs[k], ys[k], zs[k]);
-        } else {
-            xs[k] = 0.0f;
-            ys[k] = 0.0f;
-            zs[k] = 0.0f;
-        }
+        const uint32_t i = min(base + k * 256u + tid, c.n - 1u);
+        load_point<DIM>(c.pos, i, xs[k], ys[k], zs[k]);
     }
 }
 
@@ -222,9 +218,9 @@ __global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
     float xs[PPT], ys[PPT], zs[PPT];
     load_chunk<DIM, PPT>(a.c, base, xs, ys, zs);
     __syncthreads();
-    const CloudArgs& c = a.c;
+    const CloudArgs c = a.c;  // by value: the key schedule is then shared by all points
     bin_view<DIM, PPT>(a.v, c.n, blockIdx.x, base, a.shift, a.stamp, xs, ys, zs, stage, hist,
-                       wave_sum, [&](uint32_t i, float& x, float& y, float& z) {
+                       wave_sum, [c](uint32_t i, float& x, float& y, float& z) {
                            if constexpr ((PHASE & kDisplace) != 0) {
                                displace<DIM, WRAP>(c, c.step, i, x, y, z);
                                store_point<DIM>(c.pos, i, x, y, z);

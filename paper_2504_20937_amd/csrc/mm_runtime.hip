@@ -403,6 +403,8 @@ mm_status mm_destroy_instance(mm_instance inst) {
     if (!inst) return fail(MM_ERR_INVALID_ARG, "destroy_instance: null instance");
     DeviceGuard guard(inst->device);
     MM_HIP(hipStreamSynchronize(inst->stream));
+    std::vector<mm_server> servers(inst->servers.begin(), inst->servers.end());
+    for (mm_server v : servers) mm_destroy_server(v);
     std::vector<mm_batch> batches(inst->batches.begin(), inst->batches.end());
     for (mm_batch b : batches) mm_destroy_batch(b);
     std::vector<mm_view> views(inst->views.begin(), inst->views.end());

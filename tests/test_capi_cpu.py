@@ -128,3 +128,27 @@ def test_batch_struct_layouts_match_the_header(tmp_path):
         exprs.append(f"sizeof({cname})")
         expect.append(C.sizeof(py))
     assert _c_layout(tmp_path, exprs) == expect
+
+
+def test_server_calls_reject_null_arguments_without_a_device():
+    L = mm.lib()
+    assert L.mm_create_server(None, None, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_destroy_server(None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_server_add_cloud(None, None, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_server_submit(None, 0, 0, None, 2, 2, None, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_server_poll(None, 1, None, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_server_wait(None, 1, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_server_close_session(None, 0) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_server_stats_get(None, None) == mm.MM_ERR_INVALID_ARG
+
+
+def test_server_struct_layouts_match_the_header(tmp_path):
+    exprs, expect = [], []
+    for cname, py in {"mm_server_desc": mm.mm_server_desc,
+                      "mm_server_stats": mm.mm_server_stats}.items():
+        for fname, _ in py._fields_:
+            exprs.append(f"offsetof({cname}, {fname})")
+            expect.append(getattr(py, fname).offset)
+        exprs.append(f"sizeof({cname})")
+        expect.append(C.sizeof(py))
+    assert _c_layout(tmp_path, exprs) == expect

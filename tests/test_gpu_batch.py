@@ -55,6 +55,11 @@ class Batch:
         self.mm.mm_batch_render(self.b)
         self.check("render only")
 
+    def check_positions(self, what):
+        for j, dev in enumerate(self.devs):
+            pos = self.rig.positions(dev)
+            assert same_bits(pos, self.ref[j]), f"{what}, cloud {j} positions: {first_diff(pos, self.ref[j])}"
+
     def check(self, what, views=None):
         for k in (range(len(self.views)) if views is None else views):
             c, w, h, cam = self.views[k]
@@ -258,4 +263,36 @@ def test_batch_profile(rig):
     t = rig.mm.mm_batch_profile_end(b.b, 4)
     assert t.shape == (4,) and np.all(t > 0) and np.all(t < 1000)
     b.check("after profiled frames")
+    b.close()
+
+
+def test_autotune_restores_positions_and_keeps_parity(rig, tmp_path, monkeypatch):
+    mm = rig.mm
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("MM_TUNE_CACHE", str(cache))
+    say("case: autotune of a plain view (3D, 60000 points, 640x360) and of a batch")
+    pts = synth.gaussian_mixture(60000, 8)
+    dev, alloc = rig.cloud(pts)
+    cam = synth.orbit_camera(0, 640, 360)
+    view = rig.view(alloc, 60000, 3, 640, 360, 1, 4, 0.002, False, cam)
+    t = mm.mm_autotune(view, 2)
+    assert t == mm.mm_get_tuning(view) and t[0] in (mm.MM_SPLAT_DIRECT, mm.MM_SPLAT_BINNED)
+    assert np.array_equal(rig.positions(dev).view(np.uint32), pts.view(np.uint32))
+    assert cache.read_text().count("view:") == 1
+    t2 = mm.mm_autotune(view, 2)           # from the cache, no timing
+    assert t2 == t and cache.read_text().count("view:") == 1
+    ref = pts.copy()
+    mm.mm_step_render(view, 0)
+    want = oracle.step_render(ref, 4, 0, 0.002, False, cam, 640, 360, 1)
+    assert np.array_equal(mm.mm_read_frame(view, 640, 360), want)
+    mm.mm_destroy_view(view)
+
+    clouds, views = _mixed_3d()
+    b = Batch(rig, clouds, views)
+    bt = mm.mm_batch_autotune(b.b, 1)
+    assert bt == mm.mm_batch_get_tuning(b.b)
+    # the frames hold the last timed frame; the positions are as before
+    b.check_positions("after batch autotune")
+    b.step_render(0)
+    assert cache.read_text().count("batch:") == 1
     b.close()
