@@ -122,8 +122,8 @@ def bench_batched(args) -> dict:
     b = mm.mm_create_batch(inst, 3, 1, clouds, views)
     if args.autotune:
         mm.mm_batch_autotune(b, 5)
-    elif args.tile or args.ppt or args.splits or args.grid:
-        mm.mm_batch_set_tuning(b, args.tile, args.ppt, args.splits, args.grid)
+    elif args.tile or args.ppt or args.splits or args.grid or args.bin_threads:
+        mm.mm_batch_set_tuning(b, args.tile, args.ppt, args.splits, args.grid, args.bin_threads)
     tuning = mm.mm_batch_get_tuning(b)
     print(f"bench batched: {len(clouds)} clouds, {total_pts} points, {len(views)} views, "
           f"{total_px} px, tuning {tuning}", file=sys.stderr, flush=True)
@@ -202,7 +202,7 @@ def bench_batched(args) -> dict:
         "config": {"workload": "batched-64-clouds-2^12..2^22-1..4-views-256/512/1024",
                    "clouds": len(clouds), "points": total_pts, "views": len(views),
                    "pixels": total_px, "tile": tuning[0], "points_per_thread": tuning[1],
-                   "splits": tuning[2], "grid_blocks": tuning[3]},
+                   "splits": tuning[2], "grid_blocks": tuning[3], "bin_threads": tuning[4]},
         "frames_per_s": K / t_batch,
         "views_per_s": K * len(views) / t_batch,
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
@@ -248,7 +248,7 @@ def bench_served(args) -> dict:
 
     def run(rate, count, budget, seed):
         srv = mm.mm_create_server(inst, budget, args.streams, args.max_batch, 3, 1,
-                                  args.tile, args.ppt, args.splits, args.grid)
+                                  args.tile, args.ppt, args.splits, args.grid, args.bin_threads)
         for j, sp in enumerate(specs):
             mm.mm_server_add_cloud(srv, mm.make_cloud_desc(allocs[j], sizes[j], 3, sp.seed, 0.001))
         r = np.random.default_rng(seed)
@@ -397,6 +397,7 @@ def main() -> int:
     ap.add_argument("--ppt", type=int, default=0)
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0, help="batched: persistent grid blocks")
+    ap.add_argument("--bin-threads", type=int, default=0, help="threads per bin workgroup")
     ap.add_argument("--autotune", action="store_true", help="time the shapes, keep the fastest")
     ap.add_argument("--hostcopy-frames", type=int, default=10, help="hostcopy: frames timed")
     ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy"],
@@ -460,8 +461,8 @@ def main() -> int:
              "binned": mm.MM_SPLAT_BINNED}[args.splat]
     if args.autotune:
         mm.mm_autotune(view, 10)
-    elif splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits:
-        mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits)
+    elif splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits or args.bin_threads:
+        mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits, args.bin_threads)
     tuning = mm.mm_get_tuning(view)
     mode = "direct" if tuning[0] == mm.MM_SPLAT_DIRECT else "binned"
     print(f"bench: {n} points, {w}x{h}, warmup {W}, timed {K}, splat {mode} {tuning}",
@@ -505,7 +506,7 @@ def main() -> int:
                    "points": n, "width": w, "height": h, "footprint": 1,
                    "amplitude": 0.001, "graph": "one hipGraph per frame",
                    "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2],
-                   "splits": tuning[3]},
+                   "splits": tuning[3], "bin_threads": tuning[4]},
         "frames_per_s": K / elapsed,
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),

@@ -167,12 +167,16 @@ typedef struct {
     uint32_t points_per_thread; /* binned: 4, 8 or 16 (workgroup of 256 threads); 0 = auto */
     uint32_t splits;            /* binned: workgroups per tile in the depth test, 1, 2, 4
                                    or 8 (each takes a share of the points); 0 = auto */
+    uint32_t bin_threads;       /* binned: threads of a bin workgroup, 256, 512 or 1024
+                                   (a chunk is bin_threads * points_per_thread points);
+                                   0 = auto */
 } mm_tuning;
 
 /* Chooses the splat strategy and its shape for later frames; reallocates the
  * view's scratch buffers and rebuilds its graph. Synchronises. Returns
- * MM_ERR_UNSUPPORTED for a shape the screen cannot use (e.g. more than 4096
- * tiles). */
+ * MM_ERR_UNSUPPORTED for a shape the screen cannot use (more than 4096 tiles, or
+ * a bin workgroup whose LDS, 8 * bin_threads * points_per_thread + 4 * (tiles + 1)
+ * bytes, exceeds 160 KiB). */
 mm_status mm_set_tuning(mm_view view, const mm_tuning* tuning);
 
 /* The resolved strategy and shape in use (never MM_SPLAT_AUTO or 0). */
@@ -277,6 +281,7 @@ typedef struct {
     uint32_t grid_blocks;       /* 0: one workgroup per work item; else a persistent
                                    grid of that many workgroups per pass, each
                                    looping over work items */
+    uint32_t bin_threads;       /* 256, 512 or 1024; 0 = auto */
 } mm_batch_tuning;
 
 /* Chooses the shape for later frames; reallocates scratch and rebuilds the
@@ -322,7 +327,8 @@ typedef struct {
     uint32_t max_batch;         /* requests per launch: 1..4096 */
     mm_domain domain;           /* of every cloud */
     uint32_t footprint;         /* 1 or 3 */
-    mm_batch_tuning tuning;     /* tile (0: 64), points_per_thread (0: 16), splits, grid_blocks */
+    mm_batch_tuning tuning;     /* tile (0: 64), points_per_thread (0: 16), splits,
+                                   grid_blocks, bin_threads (0: 256) */
 } mm_server_desc;
 
 typedef struct {

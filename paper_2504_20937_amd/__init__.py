@@ -67,7 +67,7 @@ class mm_view_desc(C.Structure):
 
 class mm_tuning(C.Structure):
     _fields_ = [("splat", C.c_uint32), ("tile", C.c_uint32), ("points_per_thread", C.c_uint32),
-                ("splits", C.c_uint32)]
+                ("splits", C.c_uint32), ("bin_threads", C.c_uint32)]
 
 
 class mm_cloud_desc(C.Structure):
@@ -103,7 +103,7 @@ class mm_batch_desc(C.Structure):
 
 class mm_batch_tuning(C.Structure):
     _fields_ = [("tile", C.c_uint32), ("points_per_thread", C.c_uint32), ("splits", C.c_uint32),
-                ("grid_blocks", C.c_uint32)]
+                ("grid_blocks", C.c_uint32), ("bin_threads", C.c_uint32)]
 
 
 class mm_server_desc(C.Structure):
@@ -286,23 +286,23 @@ def mm_destroy_view(view: int) -> None:
 
 
 def mm_set_tuning(view: int, splat: int = MM_SPLAT_AUTO, tile: int = 0,
-                  points_per_thread: int = 0, splits: int = 0) -> None:
-    t = mm_tuning(splat, tile, points_per_thread, splits)
+                  points_per_thread: int = 0, splits: int = 0, bin_threads: int = 0) -> None:
+    t = mm_tuning(splat, tile, points_per_thread, splits, bin_threads)
     _check(lib().mm_set_tuning(view, C.byref(t)), "mm_set_tuning")
 
 
-def mm_get_tuning(view: int) -> tuple[int, int, int, int]:
-    """(splat, tile, points_per_thread, splits) in use."""
+def mm_get_tuning(view: int) -> tuple[int, int, int, int, int]:
+    """(splat, tile, points_per_thread, splits, bin_threads) in use."""
     t = mm_tuning()
     _check(lib().mm_get_tuning(view, C.byref(t)), "mm_get_tuning")
-    return t.splat, t.tile, t.points_per_thread, t.splits
+    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads
 
 
-def mm_autotune(view: int, frames: int = 10) -> tuple[int, int, int, int]:
+def mm_autotune(view: int, frames: int = 10) -> tuple[int, int, int, int, int]:
     """Times the supported shapes, keeps the fastest; returns it as mm_get_tuning does."""
     t = mm_tuning()
     _check(lib().mm_autotune(view, frames, C.byref(t)), "mm_autotune")
-    return t.splat, t.tile, t.points_per_thread, t.splits
+    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads
 
 
 def mm_set_camera(view: int, view_proj) -> None:
@@ -427,22 +427,22 @@ def mm_batch_read_frame(batch: int, view: int, width: int, height: int) -> np.nd
 
 
 def mm_batch_set_tuning(batch: int, tile: int = 0, points_per_thread: int = 0, splits: int = 0,
-                        grid_blocks: int = 0) -> None:
-    t = mm_batch_tuning(tile, points_per_thread, splits, grid_blocks)
+                        grid_blocks: int = 0, bin_threads: int = 0) -> None:
+    t = mm_batch_tuning(tile, points_per_thread, splits, grid_blocks, bin_threads)
     _check(lib().mm_batch_set_tuning(batch, C.byref(t)), "mm_batch_set_tuning")
 
 
-def mm_batch_get_tuning(batch: int) -> tuple[int, int, int, int]:
-    """(tile, points_per_thread, splits, grid_blocks) in use."""
+def mm_batch_get_tuning(batch: int) -> tuple[int, int, int, int, int]:
+    """(tile, points_per_thread, splits, grid_blocks, bin_threads) in use."""
     t = mm_batch_tuning()
     _check(lib().mm_batch_get_tuning(batch, C.byref(t)), "mm_batch_get_tuning")
-    return t.tile, t.points_per_thread, t.splits, t.grid_blocks
+    return t.tile, t.points_per_thread, t.splits, t.grid_blocks, t.bin_threads
 
 
-def mm_batch_autotune(batch: int, frames: int = 5) -> tuple[int, int, int, int]:
+def mm_batch_autotune(batch: int, frames: int = 5) -> tuple[int, int, int, int, int]:
     t = mm_batch_tuning()
     _check(lib().mm_batch_autotune(batch, frames, C.byref(t)), "mm_batch_autotune")
-    return t.tile, t.points_per_thread, t.splits, t.grid_blocks
+    return t.tile, t.points_per_thread, t.splits, t.grid_blocks, t.bin_threads
 
 
 def mm_batch_profile_begin(batch: int, capacity: int) -> None:
@@ -460,13 +460,13 @@ def mm_batch_profile_end(batch: int, capacity: int) -> np.ndarray:
 # -------------------------------------------------------------------- server
 def mm_create_server(inst: int, fb_budget_bytes: int, streams: int = 2, max_batch: int = 256,
                      dim: int = 3, footprint: int = 1, tile: int = 0, points_per_thread: int = 0,
-                     splits: int = 0, grid_blocks: int = 0) -> int:
+                     splits: int = 0, grid_blocks: int = 0, bin_threads: int = 0) -> int:
     d = mm_server_desc()
     d.fb_budget_bytes = fb_budget_bytes
     d.streams, d.max_batch = streams, max_batch
     d.domain = MM_DOMAIN_2D if dim == 2 else MM_DOMAIN_3D
     d.footprint = footprint
-    d.tuning = mm_batch_tuning(tile, points_per_thread, splits, grid_blocks)
+    d.tuning = mm_batch_tuning(tile, points_per_thread, splits, grid_blocks, bin_threads)
     out = _vp()
     _check(lib().mm_create_server(inst, C.byref(d), C.byref(out)), "mm_create_server")
     return out.value

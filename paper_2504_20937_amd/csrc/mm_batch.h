@@ -67,8 +67,8 @@ void bind_args(const TableImage& img, const unsigned char* dstat, const unsigned
                mm::BatchTileArgs& t, mm::BatchTileArgs& m);
 // The launch sequence: bin, displace-only (if any), tile, merge, seam (3x3).
 std::vector<Node> make_nodes(mm_domain domain, uint32_t footprint, uint32_t shift, uint32_t ppt,
-                             const TableImage& img, uint32_t grid_blocks, mm::BatchBinArgs* b,
-                             mm::BatchTileArgs* t, mm::BatchTileArgs* m);
+                             uint32_t threads, const TableImage& img, uint32_t grid_blocks,
+                             mm::BatchBinArgs* b, mm::BatchTileArgs* t, mm::BatchTileArgs* m);
 void xcd_tile_items(const std::vector<PlanView>& views, std::vector<uint2>& out);
 
 struct Plan {
@@ -80,7 +80,7 @@ struct Plan {
     std::vector<PlanView> views;  // grouped by cloud, in cloud order
 
     mm_batch_tuning tuning{};
-    uint32_t shift = 5, ppt = 16, P = 4096, total_tiles = 0;
+    uint32_t shift = 5, ppt = 16, threads = 256, P = 4096, total_tiles = 0;
     uint32_t* active = nullptr;   // tile stamps of all views, then the frame stamp
     uint32_t stamp = 0;
     TableImage img;

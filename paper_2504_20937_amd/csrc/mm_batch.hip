@@ -68,21 +68,27 @@ mm_status Plan::resolve(const mm_batch_tuning& req, mm_batch_tuning& out) const 
     for (const PlanView& v : views) worst32 = std::max(worst32, tiles_of(v.width, v.height, 32));
     if (out.tile == 0) out.tile = worst32 <= kMaxTiles ? 32u : 64u;
     if (out.points_per_thread == 0) out.points_per_thread = 16;
+    if (out.bin_threads == 0) out.bin_threads = 256;
     const uint32_t shift = shift_of(out.tile);
     if (!mm::binned_shape_ok(static_cast<int>(shift), static_cast<int>(out.points_per_thread),
-                             out.splits == 0 ? 1u : out.splits))
+                             out.bin_threads, out.splits == 0 ? 1u : out.splits))
         return fail(MM_ERR_INVALID_ARG,
-                    "batch tuning: tile %u / points_per_thread %u / splits %u not in "
-                    "{16,32,64} x {4,8,16} x {0,1,2,4,8}",
-                    out.tile, out.points_per_thread, out.splits);
+                    "batch tuning: tile %u / points_per_thread %u / bin_threads %u / splits %u not in "
+                    "{16,32,64} x {4,8,16} x {256,512,1024} x {0,1,2,4,8}",
+                    out.tile, out.points_per_thread, out.bin_threads, out.splits);
     if (out.grid_blocks != 0 && (out.grid_blocks % 8 != 0 || out.grid_blocks > (1u << 20)))
         return fail(MM_ERR_INVALID_ARG,
                     "batch tuning: grid_blocks %u is not 0 or a multiple of 8 up to 2^20",
                     out.grid_blocks);
-    for (const PlanView& v : views)
-        if (tiles_of(v.width, v.height, out.tile) > kMaxTiles)
+    for (const PlanView& v : views) {
+        const uint32_t nt = tiles_of(v.width, v.height, out.tile);
+        if (nt > kMaxTiles)
             return fail(MM_ERR_UNSUPPORTED, "batch tuning: a %ux%u view needs %u tiles of %u px (max %u)",
-                        v.width, v.height, tiles_of(v.width, v.height, out.tile), out.tile, kMaxTiles);
+                        v.width, v.height, nt, out.tile, kMaxTiles);
+        const size_t lds = mm::bin_lds_bytes(static_cast<int>(out.points_per_thread), out.bin_threads, nt);
+        if (lds + 1024 > mm::kMaxLdsBytes)
+            return fail(MM_ERR_UNSUPPORTED, "batch tuning: a bin workgroup would need %zu bytes of LDS", lds);
+    }
     return MM_OK;
 }
 
@@ -234,14 +240,15 @@ void bind_args(const TableImage& img, const unsigned char* dstat, const unsigned
 }
 
 std::vector<Node> make_nodes(mm_domain domain, uint32_t footprint, uint32_t shift, uint32_t ppt,
-                             const TableImage& img, uint32_t grid_blocks, mm::BatchBinArgs* b,
-                             mm::BatchTileArgs* t, mm::BatchTileArgs* m) {
+                             uint32_t threads, const TableImage& img, uint32_t grid_blocks,
+                             mm::BatchBinArgs* b, mm::BatchTileArgs* t, mm::BatchTileArgs* m) {
     const int dim = static_cast<int>(domain), foot = static_cast<int>(footprint);
     const int sh = static_cast<int>(shift), ip = static_cast<int>(ppt);
     std::vector<Node> nodes;
-    nodes.push_back({mm::batch_bin_launch(dim, mm::kDisplaceRender, ip, img.n_bin, img.max_tiles,
-                                          grid_blocks), b});
-    if (img.n_disp) nodes.push_back({mm::batch_displace_launch(dim, ip, img.n_disp, grid_blocks), b});
+    nodes.push_back({mm::batch_bin_launch(dim, mm::kDisplaceRender, ip, threads, img.n_bin,
+                                          img.max_tiles, grid_blocks), b});
+    if (img.n_disp)
+        nodes.push_back({mm::batch_displace_launch(dim, ip, threads, img.n_disp, grid_blocks), b});
     nodes.push_back({mm::batch_tile_launch(foot, sh, img.n_tile, grid_blocks), t});
     nodes.push_back({mm::batch_merge_launch(foot, sh, img.n_merge, grid_blocks), m});
     if (foot == 3) nodes.push_back({mm::batch_seam_launch(sh, img.n_merge, grid_blocks), m});
@@ -252,7 +259,8 @@ mm_status Plan::setup(mm_instance inst, const mm_batch_tuning& t) {
     tuning = t;
     shift = shift_of(t.tile);
     ppt = t.points_per_thread;
-    P = 256u * ppt;
+    threads = t.bin_threads;
+    P = threads * ppt;
     hipStream_t s = inst->stream;
     const uint32_t side = t.tile;
     const uint32_t side_a = footprint == 3 ? side + 2 : side;
@@ -292,8 +300,9 @@ mm_status Plan::setup(mm_instance inst, const mm_batch_tuning& t) {
     ring_next = 0;
     bind_args(img, static_cast<unsigned char*>(dev_static), static_cast<unsigned char*>(dev_frame),
               active + total_tiles, shift, P, bargs, targs, margs);
-    nodes = make_nodes(domain, footprint, shift, ppt, img, t.grid_blocks, &bargs, &targs, &margs);
-    render_bin = mm::batch_bin_launch(static_cast<int>(domain), mm::kRender, static_cast<int>(ppt),
+    nodes = make_nodes(domain, footprint, shift, ppt, threads, img, t.grid_blocks, &bargs, &targs,
+                       &margs);
+    render_bin = mm::batch_bin_launch(static_cast<int>(domain), mm::kRender, static_cast<int>(ppt), threads,
                                       img.n_bin, img.max_tiles, t.grid_blocks);
     return MM_OK;
 }
@@ -462,7 +471,7 @@ mm_status mm_create_batch(mm_instance inst, const mm_batch_desc* desc, mm_batch*
     }
     mm_status st = e == hipSuccess ? MM_OK : hip_fail(e, "create_batch: frame buffers");
     mm_batch_tuning t{};
-    if (st == MM_OK) st = p.resolve(mm_batch_tuning{0, 0, 0, 0}, t);
+    if (st == MM_OK) st = p.resolve(mm_batch_tuning{0, 0, 0, 0, 0}, t);
     if (st == MM_OK) st = p.setup(inst, t);
     if (st == MM_OK) st = p.build_graph();
     if (st != MM_OK) {
@@ -607,9 +616,9 @@ mm_status mm_batch_autotune(mm_batch b, uint32_t frames, mm_batch_tuning* out) {
     char key[256];
     std::snprintf(key, sizeof key, "batch:%s:d%d:f%u:c%zu:v%zu:%016llx", device_arch(inst->device).c_str(),
                   (int)p.domain, p.footprint, p.clouds.size(), p.views.size(), (unsigned long long)h);
-    uint32_t cached[4];
+    uint32_t cached[kTuneValues];
     if (tune_cache_lookup(key, cached)) {
-        const mm_batch_tuning t{cached[0], cached[1], cached[2], cached[3]};
+        const mm_batch_tuning t{cached[0], cached[1], cached[2], cached[3], cached[4]};
         if (mm_batch_set_tuning(b, &t) == MM_OK) return mm_batch_get_tuning(b, out);
     }
     // save every cloud
@@ -624,20 +633,22 @@ mm_status mm_batch_autotune(mm_batch b, uint32_t frames, mm_batch_tuning* out) {
     }
     mm_batch_tuning best{};
     float best_ms = 0.0f;
-    for (uint32_t tile : {16u, 32u, 64u})
-        for (uint32_t ppt : {8u, 16u})
-            for (uint32_t splits : {0u, 1u, 2u})
-                for (uint32_t grid : {0u, 2048u}) {
-                    if (e != hipSuccess) break;
-                    const mm_batch_tuning c{tile, ppt, splits, grid};
-                    mm_batch_tuning r{};
-                    if (p.resolve(c, r) != MM_OK || mm_batch_set_tuning(b, &c) != MM_OK) continue;
-                    const float ms = time_frames(inst->stream, frames, [&] { return mm_batch_step_render(b, 0); });
-                    if (ms > 0.0f && (best_ms == 0.0f || ms < best_ms)) {
-                        best_ms = ms;
-                        best = r;
+    for (uint32_t tile : {32u, 64u})
+        for (uint32_t threads : {256u, 512u, 1024u})
+            for (uint32_t ppt : {8u, 16u})
+                for (uint32_t splits : {0u, 1u})
+                    for (uint32_t grid : {0u, 2048u}) {
+                        if (e != hipSuccess) break;
+                        const mm_batch_tuning c{tile, ppt, splits, grid, threads};
+                        mm_batch_tuning r{};
+                        if (p.resolve(c, r) != MM_OK || mm_batch_set_tuning(b, &c) != MM_OK) continue;
+                        const float ms =
+                            time_frames(inst->stream, frames, [&] { return mm_batch_step_render(b, 0); });
+                        if (ms > 0.0f && (best_ms == 0.0f || ms < best_ms)) {
+                            best_ms = ms;
+                            best = r;
+                        }
                     }
-                }
     for (size_t c = 0; c < p.clouds.size() && e == hipSuccess; ++c)
         e = hipMemcpyAsync(p.clouds[c].args.pos, saved[c], p.clouds[c].n * stride, hipMemcpyDeviceToDevice,
                            inst->stream);
@@ -648,7 +659,8 @@ mm_status mm_batch_autotune(mm_batch b, uint32_t frames, mm_batch_tuning* out) {
     if (se != hipSuccess) return hip_fail(se, "batch_autotune: synchronising");
     if (best_ms == 0.0f) return fail(MM_ERR_HIP, "batch_autotune: no candidate ran");
     MM_TRY(mm_batch_set_tuning(b, &best));
-    const uint32_t vals[4] = {best.tile, best.points_per_thread, best.splits, best.grid_blocks};
+    const uint32_t vals[kTuneValues] = {best.tile, best.points_per_thread, best.splits,
+                                        best.grid_blocks, best.bin_threads};
     tune_cache_store(key, vals);
     return mm_batch_get_tuning(b, out);
 }

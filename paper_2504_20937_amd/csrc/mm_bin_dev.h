@@ -1,0 +1,194 @@
+// Bin pass of the binned splat: per workgroup of NT threads, a chunk of
+// P = NT * PPT consecutive points is loaded (and displaced), projected,
+// counted per screen tile in LDS, scanned, placed in LDS sorted by tile, and
+// written out as the chunk's segment of 8-byte records plus one table row of
+// u16 tile start offsets.
+//
+//   record = depth_bits << 32 | local_index << 16 | y_in_tile << 8 | x_in_tile
+//
+// Larger chunks give the tile pass longer runs per (chunk, tile) and a
+// smaller table, at the cost of LDS per workgroup (8 P + 4 (tiles + 1) bytes).
+#pragma once
+
+#include <type_traits>
+
+#include "mm_device.h"
+
+namespace mm {
+namespace bin {
+
+using namespace dev;
+
+constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, uint32_t lane) {
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan of h[0..count) in place by the NW waves of the block;
+// h[count] = total. Each wave owns a contiguous run of 64-bin blocks and
+// reads every block with consecutive lanes on consecutive words, so LDS
+// accesses never conflict.
+template <uint32_t NW>
+__device__ __forceinline__ void block_exclusive_scan(uint32_t* h, uint32_t count,
+                                                     uint32_t* wave_sum) {
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t nblk = (count + 63u) / 64u;
+    const uint32_t per = (nblk + NW - 1) / NW;
+    const uint32_t b0 = min(nblk, wave * per), b1 = min(nblk, b0 + per);
+    uint32_t lsum = 0;
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t i = b * 64u + lane;
+        lsum += i < count ? h[i] : 0u;
+    }
+    const uint32_t wtot = __shfl(wave_inclusive_scan(lsum, lane), 63, 64);
+    if (lane == 0) wave_sum[wave] = wtot;
+    __syncthreads();
+    uint32_t carry = 0, total = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < NW; ++w) {
+        carry += w < wave ? wave_sum[w] : 0u;
+        total += wave_sum[w];
+    }
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t i = b * 64u + lane;
+        const uint32_t v = i < count ? h[i] : 0u;
+        const uint32_t inc = wave_inclusive_scan(v, lane);
+        if (i < count) h[i] = carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+    }
+    if (tid == 0) h[count] = total;
+}
+
+// The PPT points per thread of chunk [base, base + P). Lanes past the end of
+// the cloud load its last point instead (their values are never used): no
+// branch around the loads, so all PPT loads are in flight together.
+template <int DIM, int PPT, uint32_t NT>
+__device__ __forceinline__ void load_chunk(const CloudArgs& c, uint32_t base, float (&xs)[PPT],
+                                           float (&ys)[PPT], float (&zs)[PPT]) {
+    const uint32_t tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint32_t i = min(base + k * NT + tid, c.n - 1u);
+        load_point<DIM>(c.pos, i, xs[k], ys[k], zs[k]);
+    }
+}
+
+// One step of point i of cloud c with the cloud's own fold limit, stored back.
+template <int DIM>
+__device__ __forceinline__ void displace_cloud(const CloudArgs& c, uint32_t i, float& x, float& y,
+                                               float& z) {
+    displace<DIM, false>(c, c.step, i, x, y, z);
+    x = fold_to(x, c.fold_lim);
+    y = fold_to(y, c.fold_lim);
+    if constexpr (DIM == 3) z = fold_to(z, c.fold_lim);
+    store_point<DIM>(c.pos, i, x, y, z);
+}
+
+// Bin one chunk of points into the tiles of one view: segment `chunk` of
+// v.seg, row `chunk` of v.table, and the stamps of the tiles that received
+// points. pre(i, x, y, z) runs on each point before its projection, in the
+// same loop (the displacement: its stores then drain under the projection
+// and histogram work). On entry hist[0..ntiles] is zero and visible to the
+// whole block.
+template <int DIM, int PPT, uint32_t NT, typename Pre>
+__device__ __forceinline__ void bin_view(const BinView& v, uint32_t n, uint32_t chunk,
+                                         uint32_t base, uint32_t shift, uint32_t stamp,
+                                         float (&xs)[PPT], float (&ys)[PPT], float (&zs)[PPT],
+                                         uint64_t* stage, uint32_t* hist, uint32_t* wave_sum,
+                                         Pre pre) {
+    constexpr uint32_t P = NT * PPT;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nt = v.ntiles;
+    const uint32_t mask = (1u << shift) - 1u;
+
+    uint32_t pix[PPT], dep[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint32_t i = base + k * NT + tid;
+        pix[k] = kNoPixel;
+        dep[k] = 0u;
+        if (i < n) {
+            pre(i, xs[k], ys[k], zs[k]);
+            int32_t px, py;
+            uint32_t bits;
+            if (project<DIM>(v.g, xs[k], ys[k], zs[k], px, py, bits)) {
+                const uint32_t ux = static_cast<uint32_t>(px), uy = static_cast<uint32_t>(py);
+                pix[k] = (uy << 16) | ux;
+                dep[k] = bits;
+                atomicAdd(&hist[(uy >> shift) * v.tiles_x + (ux >> shift)], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    block_exclusive_scan<NT / 64>(hist, nt, wave_sum);
+    __syncthreads();
+
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (pix[k] == kNoPixel) continue;
+        const uint32_t ux = pix[k] & 0xFFFFu, uy = pix[k] >> 16;
+        const uint32_t slot = atomicAdd(&hist[(uy >> shift) * v.tiles_x + (ux >> shift)], 1u);
+        const uint32_t local = static_cast<uint32_t>(k) * NT + tid;
+        stage[slot] = (static_cast<uint64_t>(dep[k]) << 32) |
+                      static_cast<uint64_t>((local << 16) | ((uy & mask) << 8) | (ux & mask));
+    }
+    __syncthreads();
+
+    // hist[b] is now the end of bin b (= start of bin b + 1); hist[nt] the total
+    const uint32_t total = hist[nt];
+    uint64_t* seg = v.seg + static_cast<uint64_t>(chunk) * P;
+    for (uint32_t j = tid; j < total; j += NT) seg[j] = stage[j];
+    uint16_t* row = v.table + static_cast<uint64_t>(chunk) * (nt + 1u);
+    for (uint32_t b = tid; b <= nt; b += NT)
+        row[b] = static_cast<uint16_t>(b == 0 ? 0u : hist[b - 1]);
+    // Stamp the tiles that received points. All workgroups write the same
+    // value, so the stores are plain cached ones (relaxed atomics at
+    // wavefront scope carry no cache-bypass bits); the kernel boundary makes
+    // them visible to the tile pass.
+    for (uint32_t b = tid; b < nt; b += NT) {
+        const uint32_t s = b == 0 ? 0u : hist[b - 1];
+        if (hist[b] > s) store_flag(&v.active[b], stamp);
+    }
+}
+
+// LDS of a bin workgroup: the stage first, then the histogram.
+struct BinLds {
+    uint64_t* stage;
+    uint32_t* hist;
+};
+
+template <uint32_t P>
+__device__ __forceinline__ BinLds bin_lds() {
+    extern __shared__ __align__(16) unsigned char smem[];
+    return BinLds{reinterpret_cast<uint64_t*>(smem),
+                  reinterpret_cast<uint32_t*>(smem + sizeof(uint64_t) * P)};
+}
+
+// Calls fn(integral_constant<int, PPT>, integral_constant<uint32_t, NT>) for
+// the bin shape (ppt, nt): PPT in {4, 8, 16}, NT in {256, 512, 1024}.
+template <uint32_t NT, typename Fn>
+const void* dispatch_bin_ppt(int ppt, Fn fn) {
+    switch (ppt) {
+        case 4: return fn(std::integral_constant<int, 4>{}, std::integral_constant<uint32_t, NT>{});
+        case 8: return fn(std::integral_constant<int, 8>{}, std::integral_constant<uint32_t, NT>{});
+        default: return fn(std::integral_constant<int, 16>{}, std::integral_constant<uint32_t, NT>{});
+    }
+}
+
+template <typename Fn>
+const void* dispatch_bin_shape(int ppt, uint32_t nt, Fn fn) {
+    switch (nt) {
+        case 256: return dispatch_bin_ppt<256>(ppt, fn);
+        case 512: return dispatch_bin_ppt<512>(ppt, fn);
+        default: return dispatch_bin_ppt<1024>(ppt, fn);
+    }
+}
+
+}  // namespace bin
+}  // namespace mm

@@ -167,5 +167,33 @@ __device__ __forceinline__ void atomic_min_lds(uint64_t* slot, uint64_t key) {
                            __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Work tables do not change during a launch: reading them through the
+// constant address space lets the compiler use scalar loads even after the
+// kernel's own global stores, so item, cloud and view fields stay uniform
+// (SGPRs) instead of being treated as per-lane values.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+    static_assert(sizeof(T) % 4 == 0, "word-sized fields");
+    using CWord = const __attribute__((address_space(4))) uint32_t;
+    CWord* q = (CWord*)(p);
+    T out;
+    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (size_t k = 0; k < sizeof(T) / 4; ++k) o[k] = q[k];
+    return out;
+}
+
+// Per-tile frame stamps: relaxed atomics at wavefront scope, which compile to
+// plain cached loads and stores.
+__device__ __forceinline__ void store_flag(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ uint32_t load_flag(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// A padding entry of a work table: the block skips it.
+constexpr uint32_t kPadItem = 0xFFFFFFFFu;
+
 }  // namespace dev
 }  // namespace mm

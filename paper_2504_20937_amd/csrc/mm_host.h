@@ -152,10 +152,11 @@ mm_status validate_camera(const float m[16], const char* what);
 namespace mmh {
 
 // Autotuning cache: a text file named by the environment variable
-// MM_TUNE_CACHE, one "key v0 v1 v2 v3" line per tuned shape; later lines win.
+// MM_TUNE_CACHE, one "key v0 .. v4" line per tuned shape; later lines win.
 // Without the variable nothing is read or written.
-bool tune_cache_lookup(const std::string& key, uint32_t out[4]);
-void tune_cache_store(const std::string& key, const uint32_t v[4]);
+constexpr int kTuneValues = 5;
+bool tune_cache_lookup(const std::string& key, uint32_t out[kTuneValues]);
+void tune_cache_store(const std::string& key, const uint32_t v[kTuneValues]);
 // gcnArchName of a device (e.g. "gfx950:sramecc+:xnack-"), "" on failure.
 std::string device_arch(int device);
 

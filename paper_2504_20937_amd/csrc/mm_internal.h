@@ -131,20 +131,25 @@ hipError_t launch_point(const PointArgs& a, int dim, int footprint, bool wrap, P
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_fill(uint64_t* keys, uint64_t nkeys, uint64_t value, hipStream_t s);
 
-// Binned splat. Tile side 1 << shift with shift in {4, 5, 6}; points per
-// thread in {4, 8, 16}; splits per tile in {1, 2, 4, 8}.
-bool binned_shape_ok(int shift, int ppt, uint32_t splits);
-size_t bin_lds_bytes(int ppt, uint32_t ntiles);
-Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t n, uint32_t ntiles);
+// Binned splat. Tile side 1 << shift with shift in {4, 5, 6}; bin workgroups
+// of `threads` in {256, 512, 1024} threads with points per thread in
+// {4, 8, 16} (chunk P = threads * ppt points); splits per tile in
+// {1, 2, 4, 8}.
+constexpr uint32_t kMaxLdsBytes = 163840;  // per workgroup on gfx950
+bool binned_shape_ok(int shift, int ppt, uint32_t threads, uint32_t splits);
+size_t bin_lds_bytes(int ppt, uint32_t threads, uint32_t ntiles);
+Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t threads, uint32_t n,
+                  uint32_t ntiles);
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits);
 Launch merge_launch(int footprint, int shift, uint32_t ntiles);
 Launch seam_launch(int shift, uint32_t ntiles);
 
-// Batched binned splat. grid_blocks = 0 launches one block per
-// item; otherwise the launch is persistent, each block looping over items.
-Launch batch_bin_launch(int dim, Phase phase, int ppt, uint32_t items, uint32_t max_tiles,
-                        uint32_t grid_blocks);
-Launch batch_displace_launch(int dim, int ppt, uint32_t items, uint32_t grid_blocks);
+// Batched binned splat. grid_blocks = 0 launches one block per item;
+// otherwise the launch is persistent, each block looping over items.
+Launch batch_bin_launch(int dim, Phase phase, int ppt, uint32_t threads, uint32_t items,
+                        uint32_t max_tiles, uint32_t grid_blocks);
+Launch batch_displace_launch(int dim, int ppt, uint32_t threads, uint32_t items,
+                             uint32_t grid_blocks);
 Launch batch_tile_launch(int footprint, int shift, uint32_t items, uint32_t grid_blocks);
 Launch batch_merge_launch(int footprint, int shift, uint32_t items, uint32_t grid_blocks);
 Launch batch_seam_launch(int shift, uint32_t items, uint32_t grid_blocks);

@@ -150,25 +150,32 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
         out.tile = 0;
         out.points_per_thread = 0;
         out.splits = 0;
+        out.bin_threads = 0;
         return MM_OK;
     }
     if (out.tile == 0) out.tile = tiles(32) <= 4096u ? 32u : 64u;
     if (out.points_per_thread == 0) out.points_per_thread = 16;
+    if (out.bin_threads == 0) out.bin_threads = 256;
     if (out.splits == 0) {
         // enough workgroups per tile to spread the densest tiles over the
         // chip once the bin workgroups are many
-        const uint64_t wgs = (d.element_count + 256ull * out.points_per_thread - 1) /
-                             (256ull * out.points_per_thread);
+        const uint64_t P = static_cast<uint64_t>(out.bin_threads) * out.points_per_thread;
+        const uint64_t wgs = (d.element_count + P - 1) / P;
         out.splits = wgs >= 256 ? 2u : 1u;
     }
     if (!mm::binned_shape_ok(static_cast<int>(shift_of(out.tile)), static_cast<int>(out.points_per_thread),
-                             out.splits))
+                             out.bin_threads, out.splits))
         return fail(MM_ERR_INVALID_ARG,
-                    "tuning: tile %u / points_per_thread %u / splits %u not in {16,32,64} x {4,8,16} x {1,2,4,8}",
-                    out.tile, out.points_per_thread, out.splits);
-    if (tiles(out.tile) > 4096u)
-        return fail(MM_ERR_UNSUPPORTED, "tuning: %ux%u screen needs %u tiles of %u px (max 4096)",
-                    d.width, d.height, tiles(out.tile), out.tile);
+                    "tuning: tile %u / points_per_thread %u / bin_threads %u / splits %u not in "
+                    "{16,32,64} x {4,8,16} x {256,512,1024} x {1,2,4,8}",
+                    out.tile, out.points_per_thread, out.bin_threads, out.splits);
+    if (tiles(out.tile) > kMaxTiles)
+        return fail(MM_ERR_UNSUPPORTED, "tuning: %ux%u screen needs %u tiles of %u px (max %u)",
+                    d.width, d.height, tiles(out.tile), out.tile, kMaxTiles);
+    const size_t lds = mm::bin_lds_bytes(static_cast<int>(out.points_per_thread), out.bin_threads,
+                                         tiles(out.tile));
+    if (lds + 1024 > mm::kMaxLdsBytes)
+        return fail(MM_ERR_UNSUPPORTED, "tuning: a bin workgroup would need %zu bytes of LDS", lds);
     return MM_OK;
 }
 
@@ -193,7 +200,8 @@ mm_status setup_splat(mm_view v) {
     } else {
         const uint32_t side = v->tuning.tile, shift = shift_of(side);
         const int ppt = static_cast<int>(v->tuning.points_per_thread);
-        const uint64_t P = 256ull * static_cast<uint64_t>(ppt);
+        const uint32_t nthreads = v->tuning.bin_threads;
+        const uint64_t P = static_cast<uint64_t>(nthreads) * static_cast<uint64_t>(ppt);
         v->tiles_x = (d.width + side - 1) / side;
         v->tiles_y = (d.height + side - 1) / side;
         v->ntiles = v->tiles_x * v->tiles_y;
@@ -243,7 +251,7 @@ mm_status setup_splat(mm_view v) {
         t.v.seed_hi = v->args.c.seed_hi;
         t.stamp_in = v->active + v->ntiles;
         t.points_per_wg = static_cast<uint32_t>(P);
-        v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, v->args.c.n, v->ntiles));
+        v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, nthreads, v->args.c.n, v->ntiles));
         v->nodes.push_back(mm::tile_launch(foot, static_cast<int>(shift), v->ntiles, v->tuning.splits));
         v->nodes.push_back(mm::merge_launch(foot, static_cast<int>(shift), v->ntiles));
         if (foot == 3) v->nodes.push_back(mm::seam_launch(static_cast<int>(shift), v->ntiles));
@@ -487,7 +495,7 @@ mm_status mm_create_view(mm_instance inst, const mm_view_desc* desc, mm_view* ou
         return fail(MM_ERR_INVALID_ARG, "create_view: position is not an alloc of this instance");
     MM_TRY(validate_desc(inst, desc));
     mm_tuning tuning{};
-    MM_TRY(resolve_tuning(*desc, mm_tuning{MM_SPLAT_AUTO, 0, 0}, tuning));
+    MM_TRY(resolve_tuning(*desc, mm_tuning{MM_SPLAT_AUTO, 0, 0, 0, 0}, tuning));
     DeviceGuard guard(inst->device);
     mm_view v = new (std::nothrow) mm_view_s();
     if (!v) return fail(MM_ERR_OUT_OF_MEMORY, "create_view: host allocation");
@@ -546,19 +554,21 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     char key[256];
     std::snprintf(key, sizeof key, "view:%s:d%d:n%llu:%ux%u:f%u", device_arch(inst->device).c_str(),
                   (int)d.domain, (unsigned long long)d.element_count, d.width, d.height, d.footprint);
-    uint32_t cached[4];
+    uint32_t cached[5];
     if (tune_cache_lookup(key, cached)) {
-        const mm_tuning t{cached[0], cached[1], cached[2], cached[3]};
+        const mm_tuning t{cached[0], cached[1], cached[2], cached[3], cached[4]};
         if (mm_set_tuning(v, &t) == MM_OK) return mm_get_tuning(v, out);
     }
     const size_t bytes = static_cast<size_t>(d.element_count) * 4u * static_cast<size_t>(d.format);
     void* saved = nullptr;
     MM_HIP(hipMalloc(&saved, bytes));
     hipError_t e = hipMemcpyAsync(saved, v->position->ptr, bytes, hipMemcpyDeviceToDevice, inst->stream);
-    std::vector<mm_tuning> cands = {{MM_SPLAT_DIRECT, 0, 0, 0}};
-    for (uint32_t tile : {16u, 32u, 64u})
-        for (uint32_t ppt : {8u, 16u})
-            for (uint32_t splits : {1u, 2u, 4u}) cands.push_back({MM_SPLAT_BINNED, tile, ppt, splits});
+    std::vector<mm_tuning> cands = {{MM_SPLAT_DIRECT, 0, 0, 0, 0}};
+    for (uint32_t tile : {32u, 64u})
+        for (uint32_t threads : {256u, 512u, 1024u})
+            for (uint32_t ppt : {8u, 16u})
+                for (uint32_t splits : {1u, 2u, 4u})
+                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, splits, threads});
     mm_tuning best{};
     float best_ms = 0.0f;
     for (const mm_tuning& c : cands) {
@@ -579,7 +589,8 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     if (se != hipSuccess) return hip_fail(se, "autotune: synchronising");
     if (best_ms == 0.0f) return fail(MM_ERR_HIP, "autotune: no candidate ran");
     MM_TRY(mm_set_tuning(v, &best));
-    const uint32_t vals[4] = {best.splat, best.tile, best.points_per_thread, best.splits};
+    const uint32_t vals[5] = {best.splat, best.tile, best.points_per_thread, best.splits,
+                              best.bin_threads};
     tune_cache_store(key, vals);
     return mm_get_tuning(v, out);
 }
@@ -628,8 +639,8 @@ mm_status mm_render(mm_view v) {
     }
     MM_TRY(next_stamp(v));
     const mm::Launch b = mm::bin_launch(dim, v->desc.wrap != 0, mm::kRender,
-                                        static_cast<int>(v->tuning.points_per_thread), v->args.c.n,
-                                        v->ntiles);
+                                        static_cast<int>(v->tuning.points_per_thread),
+                                        v->tuning.bin_threads, v->args.c.n, v->ntiles);
     void* bargs[] = {&v->bargs};
     MM_HIP(hipLaunchKernel(b.func, b.grid, b.block, bargs, b.shared, s));
     for (size_t k = 1; k < v->nodes.size(); ++k) {

@@ -96,7 +96,7 @@ struct Slot {
 struct mm_server_s {
     mm_instance inst = nullptr;
     mm_server_desc desc{};
-    uint32_t side = 64, shift = 6, ppt = 16, P = 4096, splits_cap = 2;
+    uint32_t side = 64, shift = 6, ppt = 16, threads = 256, P = 4096, splits_cap = 2;
     std::mutex mu;
     std::condition_variable cv;     // scheduler wake-up
     std::condition_variable done_cv;  // request completion
@@ -327,8 +327,8 @@ mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
         stamp = 1;
     }
     sl.b.stamp = stamp;
-    sl.nodes = mmb::make_nodes(desc.domain, desc.footprint, shift, ppt, sl.img, desc.tuning.grid_blocks,
-                               &sl.b, &sl.t, &sl.m);
+    sl.nodes = mmb::make_nodes(desc.domain, desc.footprint, shift, ppt, threads, sl.img,
+                               desc.tuning.grid_blocks, &sl.b, &sl.t, &sl.m);
     for (const mmb::Node& n : sl.nodes) MM_HIP(mmh::launch(n.l, n.arg, sl.stream));
     MM_HIP(hipEventRecord(sl.done, sl.stream));
     return MM_OK;
@@ -429,7 +429,8 @@ mm_status mm_create_server(mm_instance inst, const mm_server_desc* desc, mm_serv
     const mm_batch_tuning& t = desc->tuning;
     const uint32_t side = t.tile ? t.tile : 64u;
     const uint32_t ppt = t.points_per_thread ? t.points_per_thread : 16u;
-    if (!mm::binned_shape_ok(static_cast<int>(shift_of(side)), static_cast<int>(ppt),
+    const uint32_t threads = t.bin_threads ? t.bin_threads : 256u;
+    if (!mm::binned_shape_ok(static_cast<int>(shift_of(side)), static_cast<int>(ppt), threads,
                              t.splits == 0 ? 1u : t.splits))
         return fail(MM_ERR_INVALID_ARG, "create_server: tuning %u / %u / %u not supported", side, ppt,
                     t.splits);
@@ -443,9 +444,10 @@ mm_status mm_create_server(mm_instance inst, const mm_server_desc* desc, mm_serv
     srv->side = side;
     srv->shift = shift_of(side);
     srv->ppt = ppt;
-    srv->P = 256u * ppt;
+    srv->threads = threads;
+    srv->P = threads * ppt;
     srv->splits_cap = t.splits ? t.splits : 2u;
-    srv->desc.tuning = mm_batch_tuning{side, ppt, t.splits, t.grid_blocks};
+    srv->desc.tuning = mm_batch_tuning{side, ppt, t.splits, t.grid_blocks, threads};
     hipError_t e = hipMalloc(&srv->stamps, 256 * desc->streams);
     if (e == hipSuccess) e = hipMemset(srv->stamps, 0, 256 * desc->streams);
     srv->slots.resize(desc->streams);

@@ -1,313 +1,23 @@
-// Binned splat (gfx950): the depth test runs in LDS, with no global atomics.
+// Tile side of the binned splat (gfx950): the per-tile depth test in LDS,
+// the merge of the splits with the RGBA8 resolve, and the seam pass of 3x3
+// footprints, each as a plain kernel (one view, kernel arguments) and a
+// batched kernel (items (view, tile) from a device table).
 //
-// Global 64-bit atomics execute outside the XCD's L2 on this part and top
-// out near 27 G/s whatever the address pattern, so the splat is split:
-//
-// bin kernel  (one workgroup per P = 256 * PPT consecutive points):
-//   load -> displace (+store) -> project; count points per screen tile in
-//   LDS; exclusive scan; place each point's 8-byte record in LDS sorted by
-//   tile; write the records (coalesced) as the workgroup's segment and the
-//   tile start offsets as one table row (u16). Tiles that received points
-//   are stamped active for the frame.
-//   record = depth_bits << 32 | local_index << 16 | y_in_tile << 8 | x_in_tile
-//
-// tile kernel (one workgroup per screen tile):
-//   (split into `splits` workgroups per tile, each over a share of the bin
-//   workgroups) pull the tile's column of the table into LDS, read the
-//   chunks coalesced (a group of lanes per chunk, many chunks in flight),
-//   take the min (depth_bits << 32 | index) per pixel with LDS atomics, and
-//   write the partial keys of the tile.
+// tile kernel (one workgroup per screen tile and split): pull the tile's
+//   column of the table into LDS, read the chunks coalesced (a group of lanes
+//   per chunk, many chunks in flight), take the min (depth_bits << 32 |
+//   index) per pixel with LDS atomics, and write the partial keys of the tile.
 // merge kernel (one workgroup per tile): min over the splits, resolve to
 //   RGBA8 directly: no full-screen key buffer, no clear pass. With the 3x3
 //   footprint the tile carries a one-pixel apron; edge pixels and the apron
 //   go to small global arrays, and the seam kernel merges edges across tile
 //   borders.
-//
-// The per-chunk, per-tile and per-merge work are device functions. The plain
-// kernels take one cloud and one view from their kernel arguments; the
-// batched kernels run many clouds and views in one launch per pass, each
-// block walking a list of work items held in device memory: a bin item
-// displaces its chunk once and then bins it into every view of its cloud.
 #include "mm_device.h"
 
 namespace mm {
 namespace {
 
 using namespace dev;
-
-constexpr uint32_t kNoPixel = 0xFFFFFFFFu;
-constexpr uint32_t kPadItem = 0xFFFFFFFFu;
-
-// Work tables do not change during a launch: reading them through the
-// constant address space lets the compiler use scalar loads even after the
-// kernel's own global stores, so item, cloud and view fields stay uniform
-// (SGPRs) instead of being treated as per-lane values.
-template <typename T>
-__device__ __forceinline__ T load_uniform(const T* p) {
-    static_assert(sizeof(T) % 4 == 0, "word-sized fields");
-    using CWord = const __attribute__((address_space(4))) uint32_t;
-    CWord* q = (CWord*)(p);
-    T out;
-    uint32_t* o = reinterpret_cast<uint32_t*>(&out);
-#pragma unroll
-    for (size_t k = 0; k < sizeof(T) / 4; ++k) o[k] = q[k];
-    return out;
-}
-
-__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v, uint32_t lane) {
-#pragma unroll
-    for (uint32_t d = 1; d < 64; d <<= 1) {
-        const uint32_t u = __shfl_up(v, d, 64);
-        if (lane >= d) v += u;
-    }
-    return v;
-}
-
-// Per-tile frame stamps: relaxed atomics at wavefront scope, which compile to
-// plain cached loads and stores.
-__device__ __forceinline__ void store_flag(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
-__device__ __forceinline__ uint32_t load_flag(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
-
-// Exclusive scan of h[0..count) in place by 256 threads; h[count] = total.
-// Each wave owns a contiguous run of 64-bin blocks and reads every block with
-// consecutive lanes on consecutive words, so LDS accesses never conflict.
-__device__ void block_exclusive_scan(uint32_t* h, uint32_t count, uint32_t* wave_sum) {
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    const uint32_t nblk = (count + 63u) / 64u;
-    const uint32_t per = (nblk + 3u) / 4u;
-    const uint32_t b0 = min(nblk, wave * per), b1 = min(nblk, b0 + per);
-    uint32_t lsum = 0;
-    for (uint32_t b = b0; b < b1; ++b) {
-        const uint32_t i = b * 64u + lane;
-        lsum += i < count ? h[i] : 0u;
-    }
-    const uint32_t wtot = __shfl(wave_inclusive_scan(lsum, lane), 63, 64);
-    if (lane == 0) wave_sum[wave] = wtot;
-    __syncthreads();
-    uint32_t carry = 0, total = 0;
-#pragma unroll
-    for (uint32_t w = 0; w < 4; ++w) {
-        carry += w < wave ? wave_sum[w] : 0u;
-        total += wave_sum[w];
-    }
-    for (uint32_t b = b0; b < b1; ++b) {
-        const uint32_t i = b * 64u + lane;
-        const uint32_t v = i < count ? h[i] : 0u;
-        const uint32_t inc = wave_inclusive_scan(v, lane);
-        if (i < count) h[i] = carry + inc - v;
-        carry += __shfl(inc, 63, 64);
-    }
-    if (tid == 0) h[count] = total;
-}
-
-// The PPT points per thread of chunk [base, base + P). Lanes past the end of
-// the cloud load its last point instead (their values are never used): no
-// branch around the loads, so all PPT loads are in flight together.
-template <int DIM, int PPT>
-__device__ __forceinline__ void load_chunk(const CloudArgs& c, uint32_t base, float (&xs)[PPT],
-                                           float (&ys)[PPT], float (&zs)[PPT]) {
-    const uint32_t tid = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint32_t i = min(base + k * 256u + tid, c.n - 1u);
-        load_point<DIM>(c.pos, i, xs[k], ys[k], zs[k]);
-    }
-}
-
-// Displace the chunk's points and store them back. Kept after the block's
-// first barrier: a barrier waits for the block's outstanding stores, and the
-// stores then drain while the projection runs.
-template <int DIM, bool WRAP, int PPT>
-__device__ __forceinline__ void displace_chunk(const CloudArgs& c, uint32_t step, uint32_t base,
-                                               float (&xs)[PPT], float (&ys)[PPT],
-                                               float (&zs)[PPT]) {
-    const uint32_t tid = threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint32_t i = base + k * 256u + tid;
-        if (i < c.n) {
-            displace<DIM, WRAP>(c, step, i, xs[k], ys[k], zs[k]);
-            store_point<DIM>(c.pos, i, xs[k], ys[k], zs[k]);
-        }
-    }
-}
-
-// Bin one chunk of points into the tiles of one view: segment `chunk` of
-// v.seg, row `chunk` of v.table, and the stamps of the tiles that received
-// points. pre(i, x, y, z) runs on each point before its projection, in the
-// same loop (the displacement: its stores then drain under the projection
-// and histogram work). On entry hist[0..ntiles] is zero and visible to the
-// whole block.
-template <int DIM, int PPT, typename Pre>
-__device__ __forceinline__ void bin_view(const BinView& v, uint32_t n, uint32_t chunk,
-                                         uint32_t base, uint32_t shift, uint32_t stamp,
-                                         float (&xs)[PPT], float (&ys)[PPT], float (&zs)[PPT],
-                                         uint64_t* stage, uint32_t* hist, uint32_t* wave_sum,
-                                         Pre pre) {
-    constexpr uint32_t P = 256u * PPT;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t nt = v.ntiles;
-    const uint32_t mask = (1u << shift) - 1u;
-
-    uint32_t pix[PPT], dep[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const uint32_t i = base + k * 256u + tid;
-        pix[k] = kNoPixel;
-        dep[k] = 0u;
-        if (i < n) {
-            pre(i, xs[k], ys[k], zs[k]);
-            int32_t px, py;
-            uint32_t bits;
-            if (project<DIM>(v.g, xs[k], ys[k], zs[k], px, py, bits)) {
-                const uint32_t ux = static_cast<uint32_t>(px), uy = static_cast<uint32_t>(py);
-                pix[k] = (uy << 16) | ux;
-                dep[k] = bits;
-                atomicAdd(&hist[(uy >> shift) * v.tiles_x + (ux >> shift)], 1u);
-            }
-        }
-    }
-    __syncthreads();
-    block_exclusive_scan(hist, nt, wave_sum);
-    __syncthreads();
-
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        if (pix[k] == kNoPixel) continue;
-        const uint32_t ux = pix[k] & 0xFFFFu, uy = pix[k] >> 16;
-        const uint32_t slot = atomicAdd(&hist[(uy >> shift) * v.tiles_x + (ux >> shift)], 1u);
-        const uint32_t local = static_cast<uint32_t>(k) * 256u + tid;
-        stage[slot] = (static_cast<uint64_t>(dep[k]) << 32) |
-                      static_cast<uint64_t>((local << 16) | ((uy & mask) << 8) | (ux & mask));
-    }
-    __syncthreads();
-
-    // hist[b] is now the end of bin b (= start of bin b + 1); hist[nt] the total
-    const uint32_t total = hist[nt];
-    uint64_t* seg = v.seg + static_cast<uint64_t>(chunk) * P;
-    for (uint32_t j = tid; j < total; j += 256u) seg[j] = stage[j];
-    uint16_t* row = v.table + static_cast<uint64_t>(chunk) * (nt + 1u);
-    for (uint32_t b = tid; b <= nt; b += 256u)
-        row[b] = static_cast<uint16_t>(b == 0 ? 0u : hist[b - 1]);
-    // Stamp the tiles that received points. All workgroups write the same
-    // value, so the stores are plain cached ones (relaxed atomics at
-    // wavefront scope carry no cache-bypass bits); the kernel boundary makes
-    // them visible to the tile pass.
-    for (uint32_t b = tid; b < nt; b += 256u) {
-        const uint32_t s = b == 0 ? 0u : hist[b - 1];
-        if (hist[b] > s) store_flag(&v.active[b], stamp);
-    }
-}
-
-template <int DIM, bool WRAP, int PHASE, int PPT>
-__global__ __launch_bounds__(256) void bin_kernel(BinArgs a) {
-    constexpr uint32_t P = 256u * PPT;
-    extern __shared__ __align__(16) unsigned char smem[];
-    uint64_t* stage = reinterpret_cast<uint64_t*>(smem);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(smem + sizeof(uint64_t) * P);
-    __shared__ uint32_t wave_sum[4];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t base = blockIdx.x * P;
-
-    for (uint32_t b = tid; b <= a.v.ntiles; b += 256u) hist[b] = 0u;
-    if (blockIdx.x == 0 && tid == 0) *a.stamp_out = a.stamp;
-    float xs[PPT], ys[PPT], zs[PPT];
-    load_chunk<DIM, PPT>(a.c, base, xs, ys, zs);
-    __syncthreads();
-    const CloudArgs c = a.c;  // by value: the key schedule is then shared by all points
-    bin_view<DIM, PPT>(a.v, c.n, blockIdx.x, base, a.shift, a.stamp, xs, ys, zs, stage, hist,
-                       wave_sum, [c](uint32_t i, float& x, float& y, float& z) {
-                           if constexpr ((PHASE & kDisplace) != 0) {
-                               displace<DIM, WRAP>(c, c.step, i, x, y, z);
-                               store_point<DIM>(c.pos, i, x, y, z);
-                           }
-                       });
-}
-
-// One step of point i of cloud c with the cloud's own fold limit.
-template <int DIM>
-__device__ __forceinline__ void displace_cloud(const CloudArgs& c, uint32_t i, float& x, float& y,
-                                               float& z) {
-    displace<DIM, false>(c, c.step, i, x, y, z);
-    x = fold_to(x, c.fold_lim);
-    y = fold_to(y, c.fold_lim);
-    if constexpr (DIM == 3) z = fold_to(z, c.fold_lim);
-    store_point<DIM>(c.pos, i, x, y, z);
-}
-
-// Items (cloud, chunk): displace the chunk once, then bin it into each of the
-// cloud's views in turn, reusing the LDS stage and histogram. Each cloud
-// carries its own step and fold limit. PERSIST: each block loops over items
-// blockIdx.x, blockIdx.x + gridDim.x, ...; else one item per block.
-template <int DIM, int PHASE, int PPT, bool PERSIST>
-__global__ __launch_bounds__(256) void batch_bin_kernel(BatchBinArgs a) {
-    constexpr uint32_t P = 256u * PPT;
-    extern __shared__ __align__(16) unsigned char smem[];
-    uint64_t* stage = reinterpret_cast<uint64_t*>(smem);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(smem + sizeof(uint64_t) * P);
-    __shared__ uint32_t wave_sum[4];
-    const uint32_t tid = threadIdx.x;
-    if (blockIdx.x == 0 && tid == 0) *a.stamp_out = a.stamp;
-    auto run_item = [&](uint32_t it) {
-        const uint2 item = load_uniform(&a.item[it]);
-        const CloudArgs c = load_uniform(&a.clouds[item.x]);
-        const uint32_t base = item.y * P;
-        const uint32_t v0 = load_uniform(&a.first_view[item.x]);
-        const uint32_t v1 = load_uniform(&a.first_view[item.x + 1]);
-        for (uint32_t b = tid; b <= load_uniform(&a.views[v0].ntiles); b += 256u) hist[b] = 0u;
-        float xs[PPT], ys[PPT], zs[PPT];
-        load_chunk<DIM, PPT>(c, base, xs, ys, zs);
-        __syncthreads();
-        // the first view displaces
-        bin_view<DIM, PPT>(load_uniform(&a.views[v0]), c.n, item.y, base, a.shift, a.stamp, xs, ys,
-                           zs, stage, hist, wave_sum, [&](uint32_t i, float& x, float& y, float& z) {
-                               if constexpr ((PHASE & kDisplace) != 0) displace_cloud<DIM>(c, i, x, y, z);
-                           });
-        __syncthreads();  // stage and hist free for the next view or item
-        // Further views read the (displaced) chunk again, mostly from L2:
-        // keeping it, or its addresses, in registers across the first view
-        // costs more in occupancy than the reload. The empty asm hides that
-        // base2 equals base, so the addresses are formed anew.
-        uint32_t base2 = base;
-        asm volatile("" : "+v"(base2));
-        for (uint32_t vi = v0 + 1; vi < v1; ++vi) {
-            const BinView v = load_uniform(&a.views[vi]);
-            for (uint32_t b = tid; b <= v.ntiles; b += 256u) hist[b] = 0u;
-            load_chunk<DIM, PPT>(c, base2, xs, ys, zs);
-            __syncthreads();
-            bin_view<DIM, PPT>(v, c.n, item.y, base2, a.shift, a.stamp, xs, ys, zs, stage, hist,
-                               wave_sum, [](uint32_t, float&, float&, float&) {});
-            __syncthreads();
-        }
-    };
-    if constexpr (PERSIST) {
-        for (uint32_t it = blockIdx.x; it < a.items; it += gridDim.x) run_item(it);
-    } else {
-        if (blockIdx.x < a.items) run_item(blockIdx.x);
-    }
-}
-
-// Items (cloud, chunk) of clouds without views: displacement only.
-template <int DIM, int PPT>
-__global__ __launch_bounds__(256) void batch_displace_kernel(BatchBinArgs a) {
-    constexpr uint32_t P = 256u * PPT;
-    for (uint32_t it = blockIdx.x; it < a.disp_items; it += gridDim.x) {
-        const uint2 item = load_uniform(&a.disp_item[it]);
-        const CloudArgs c = load_uniform(&a.clouds[item.x]);
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const uint32_t i = item.y * P + k * 256u + threadIdx.x;
-            if (i >= c.n) continue;
-            float x, y, z;
-            load_point<DIM>(c.pos, i, x, y, z);
-            displace_cloud<DIM>(c, i, x, y, z);
-        }
-    }
-}
 
 // 64 consecutive tiles share one 128-byte line of every table row; blocks go
 // round-robin over the 8 XCDs, so each run of 64 tiles (for one split of the
@@ -643,51 +353,6 @@ __global__ __launch_bounds__(256) void batch_seam_kernel(BatchTileArgs a) {
     }
 }
 
-template <int DIM, bool WRAP, int PPT>
-const void* pick_bin_phase(Phase phase) {
-    if (phase == kRender) return reinterpret_cast<const void*>(&bin_kernel<DIM, WRAP, kRender, PPT>);
-    return reinterpret_cast<const void*>(&bin_kernel<DIM, WRAP, kDisplaceRender, PPT>);
-}
-
-template <int DIM, bool WRAP>
-const void* pick_bin_ppt(int ppt, Phase phase) {
-    switch (ppt) {
-        case 4: return pick_bin_phase<DIM, WRAP, 4>(phase);
-        case 8: return pick_bin_phase<DIM, WRAP, 8>(phase);
-        default: return pick_bin_phase<DIM, WRAP, 16>(phase);
-    }
-}
-
-const void* pick_bin(int dim, bool wrap, int ppt, Phase phase) {
-    if (dim == 2) return wrap ? pick_bin_ppt<2, true>(ppt, phase) : pick_bin_ppt<2, false>(ppt, phase);
-    return wrap ? pick_bin_ppt<3, true>(ppt, phase) : pick_bin_ppt<3, false>(ppt, phase);
-}
-
-template <int DIM, int PPT, bool PERSIST>
-const void* pick_batch_bin_phase(Phase phase) {
-    if (phase == kRender)
-        return reinterpret_cast<const void*>(&batch_bin_kernel<DIM, kRender, PPT, PERSIST>);
-    return reinterpret_cast<const void*>(&batch_bin_kernel<DIM, kDisplaceRender, PPT, PERSIST>);
-}
-
-template <int DIM, bool PERSIST>
-const void* pick_batch_bin_ppt(int ppt, Phase phase) {
-    switch (ppt) {
-        case 4: return pick_batch_bin_phase<DIM, 4, PERSIST>(phase);
-        case 8: return pick_batch_bin_phase<DIM, 8, PERSIST>(phase);
-        default: return pick_batch_bin_phase<DIM, 16, PERSIST>(phase);
-    }
-}
-
-template <int DIM>
-const void* pick_batch_displace(int ppt) {
-    switch (ppt) {
-        case 4: return reinterpret_cast<const void*>(&batch_displace_kernel<DIM, 4>);
-        case 8: return reinterpret_cast<const void*>(&batch_displace_kernel<DIM, 8>);
-        default: return reinterpret_cast<const void*>(&batch_displace_kernel<DIM, 16>);
-    }
-}
-
 template <int FOOT, int SHIFT>
 const void* tile_func(bool batched) {
     return batched ? reinterpret_cast<const void*>(&batch_tile_kernel<FOOT, SHIFT>)
@@ -739,25 +404,6 @@ uint32_t batch_grid(uint32_t items, uint32_t grid_blocks) {
 
 }  // namespace
 
-bool binned_shape_ok(int shift, int ppt, uint32_t splits) {
-    return (shift == 4 || shift == 5 || shift == 6) && (ppt == 4 || ppt == 8 || ppt == 16) &&
-           (splits == 1 || splits == 2 || splits == 4 || splits == 8);
-}
-
-size_t bin_lds_bytes(int ppt, uint32_t ntiles) {
-    return sizeof(uint64_t) * 256u * static_cast<uint32_t>(ppt) + sizeof(uint32_t) * (ntiles + 1u);
-}
-
-Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t n, uint32_t ntiles) {
-    Launch l;
-    l.func = pick_bin(dim, wrap, ppt, phase);
-    const uint64_t P = 256ull * static_cast<uint64_t>(ppt);
-    l.block = dim3(256);
-    l.grid = dim3(static_cast<uint32_t>((static_cast<uint64_t>(n) + P - 1) / P));
-    l.shared = static_cast<uint32_t>(bin_lds_bytes(ppt, ntiles));
-    return l;
-}
-
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits) {
     Launch l;
     l.func = footprint == 3 ? pick_tile<3>(shift, false) : pick_tile<1>(shift, false);
@@ -781,29 +427,6 @@ Launch seam_launch(int shift, uint32_t ntiles) {
     l.func = pick_seam(shift, false);
     l.block = dim3(256);
     l.grid = dim3(ntiles);
-    l.shared = 0;
-    return l;
-}
-
-Launch batch_bin_launch(int dim, Phase phase, int ppt, uint32_t items, uint32_t max_tiles,
-                        uint32_t grid_blocks) {
-    Launch l;
-    const bool persist = grid_blocks != 0 && grid_blocks < items;
-    if (dim == 2)
-        l.func = persist ? pick_batch_bin_ppt<2, true>(ppt, phase) : pick_batch_bin_ppt<2, false>(ppt, phase);
-    else
-        l.func = persist ? pick_batch_bin_ppt<3, true>(ppt, phase) : pick_batch_bin_ppt<3, false>(ppt, phase);
-    l.block = dim3(256);
-    l.grid = dim3(batch_grid(items, grid_blocks));
-    l.shared = static_cast<uint32_t>(bin_lds_bytes(ppt, max_tiles));
-    return l;
-}
-
-Launch batch_displace_launch(int dim, int ppt, uint32_t items, uint32_t grid_blocks) {
-    Launch l;
-    l.func = dim == 2 ? pick_batch_displace<2>(ppt) : pick_batch_displace<3>(ppt);
-    l.block = dim3(256);
-    l.grid = dim3(batch_grid(items, grid_blocks));
     l.shared = 0;
     return l;
 }

@@ -22,7 +22,7 @@ const char* cache_path() {
 }
 }  // namespace
 
-bool tune_cache_lookup(const std::string& key, uint32_t out[4]) {
+bool tune_cache_lookup(const std::string& key, uint32_t out[kTuneValues]) {
     const char* path = cache_path();
     if (!path) return false;
     std::lock_guard<std::mutex> lock(g_cache_mu);
@@ -33,23 +33,28 @@ bool tune_cache_lookup(const std::string& key, uint32_t out[4]) {
     while (std::getline(in, line)) {
         std::istringstream ss(line);
         std::string k;
-        uint32_t v[4];
-        if (!(ss >> k >> v[0] >> v[1] >> v[2] >> v[3])) continue;
+        uint32_t v[kTuneValues];
+        if (!(ss >> k)) continue;
+        bool ok = true;
+        for (int j = 0; j < kTuneValues && ok; ++j) ok = static_cast<bool>(ss >> v[j]);
+        if (!ok) continue;
         if (k == key) {
-            for (int j = 0; j < 4; ++j) out[j] = v[j];
+            for (int j = 0; j < kTuneValues; ++j) out[j] = v[j];
             found = true;  // keep reading: the last entry wins
         }
     }
     return found;
 }
 
-void tune_cache_store(const std::string& key, const uint32_t v[4]) {
+void tune_cache_store(const std::string& key, const uint32_t v[kTuneValues]) {
     const char* path = cache_path();
     if (!path) return;
     std::lock_guard<std::mutex> lock(g_cache_mu);
     std::ofstream out(path, std::ios::app);
     if (!out) return;
-    out << key << ' ' << v[0] << ' ' << v[1] << ' ' << v[2] << ' ' << v[3] << '\n';
+    out << key;
+    for (int j = 0; j < kTuneValues; ++j) out << ' ' << v[j];
+    out << '\n';
 }
 
 std::string device_arch(int device) {

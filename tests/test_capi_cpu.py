@@ -115,6 +115,7 @@ def _c_layout(tmp_path, exprs):
 
 def test_batch_struct_layouts_match_the_header(tmp_path):
     structs = {
+        "mm_tuning": mm.mm_tuning,
         "mm_cloud_desc": mm.mm_cloud_desc,
         "mm_batch_view_desc": mm.mm_batch_view_desc,
         "mm_batch_desc": mm.mm_batch_desc,

@@ -98,11 +98,13 @@ def _mixed_3d(seed=0):
     return clouds, views
 
 
-TUNINGS = [(0, 0, 0, 0), (16, 4, 1, 0), (32, 8, 2, 0), (64, 16, 4, 0), (32, 16, 0, 256),
-           (32, 8, 8, 8)]
+TUNINGS = [(0, 0, 0, 0, 0), (16, 4, 1, 0, 256), (32, 8, 2, 0, 256), (64, 16, 4, 0, 256),
+           (32, 16, 0, 256, 256), (32, 8, 8, 8, 256), (32, 16, 0, 0, 1024), (64, 8, 1, 64, 512),
+           (16, 16, 2, 0, 1024)]
 
 
-@pytest.mark.parametrize("tuning", TUNINGS, ids=[f"t{t[0]}-p{t[1]}-z{t[2]}-g{t[3]}" for t in TUNINGS])
+@pytest.mark.parametrize("tuning", TUNINGS,
+                         ids=[f"t{t[0]}-p{t[1]}-z{t[2]}-g{t[3]}-n{t[4]}" for t in TUNINGS])
 def test_batch_3d_mixed_clouds_and_screens(rig, tuning):
     say(f"case: batch 3D, 5 clouds (1..300000 points), 7 views, tuning {tuning}")
     clouds, views = _mixed_3d()
@@ -142,7 +144,7 @@ def test_batch_3x3_footprint(rig):
              (1, 330, 130, synth.orbit_camera(0, 330, 130, start_deg=200.0)),
              (2, 96, 64, synth.orbit_camera(0, 96, 64, start_deg=10.0)),
              (2, 512, 512, synth.orbit_camera(0, 512, 512, start_deg=300.0))]
-    for tuning in [(0, 0, 0, 0), (16, 8, 2, 64)]:
+    for tuning in [(0, 0, 0, 0, 0), (16, 8, 2, 64, 256), (32, 16, 1, 0, 1024)]:
         b = Batch(rig, clouds, views, foot=3)
         rig.mm.mm_batch_set_tuning(b.b, *tuning)
         for s in range(3):

@@ -50,7 +50,8 @@ def _expected(clouds, reqs, foot):
     return want, refs
 
 
-def _serve(rig, clouds, sessions, order, budget, streams, max_batch, foot=1, tuning=(0, 0, 0, 0)):
+def _serve(rig, clouds, sessions, order, budget, streams, max_batch, foot=1,
+           tuning=(0, 0, 0, 0, 0)):
     """order: [(session, cloud, frame)]; every request renders into its own buffer."""
     mm, torch = rig.mm, rig.torch
     srv = mm.mm_create_server(rig.inst, budget, streams, max_batch, 3, foot, *tuning)
@@ -154,7 +155,7 @@ def test_server_3x3_footprint(rig):
     rng = np.random.default_rng(3)
     order = [(int(rng.integers(0, 4)), int(rng.integers(0, 3)), f) for f in range(20)]
     reqs, outs, lat, stats = _serve(rig, clouds, sessions, order, 1 << 33, 2, 8, foot=3,
-                                    tuning=(16, 8, 0, 0))
+                                    tuning=(16, 8, 0, 0, 512))
     want, _ = _expected(clouds, reqs, 3)
     for k, (got, exp) in enumerate(zip(outs, want)):
         g = got.cpu().numpy().view(np.uint32)
