@@ -60,23 +60,59 @@ def measured_traffic(kernel: str):
     return (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"]) * 1024.0
 
 
-def cpu_baseline(n, w, h, frames):
-    """The oracle as it stands, single-threaded, on `frames` full frames."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def make_points(n: int, dist: str) -> np.ndarray:
+    import synth
+    return synth.uniform_cube(n, 0) if dist == "uniform" else synth.gaussian_mixture(n, 0)
+
+
+def cpu_baseline(n, w, h, frames, dist="uniform", footprint=1):
+    """The oracle as it stands, single-threaded, on `frames` frames of the
+    workload (for more than 2^24 points, of its first 2^24 points)."""
     import oracle
     import synth
 
-    pts = synth.uniform_cube(n, 0)
+    m = min(n, 1 << 24)
+    pts = make_points(n, dist)[:m].copy() if m < n else make_points(n, dist)
     depth = oracle.new_depth(w, h)
     cams = [synth.orbit_camera(f, w, h) for f in range(frames)]
     oracle.lib()
     t0 = time.perf_counter()
     for f in range(frames):
-        oracle.step_render(pts, 0, f, 0.001, False, cams[f], w, h, 1, depth)
+        oracle.step_render(pts, 0, f, 0.001, False, cams[f], w, h, footprint, depth)
     dt = time.perf_counter() - t0
-    return {"value": n * frames / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} full frames (2^{int(np.log2(n))} points, {w}x{h}), "
+    what = "full frames" if m == n else f"frames of the first 2^24 of the 2^{int(np.log2(n))} points"
+    return {"value": m * frames / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"{frames} {what} ({dist}, {w}x{h}, footprint {footprint}), "
                       f"{dt:.1f} s on one host core",
             "ms_per_frame": dt / frames * 1e3}
+
+
+def stream_copy_GBps(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """Measured device copy ceiling: bytes read + written per second."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del src, dst
+    return 2.0 * nbytes * reps / dt / 1e9
 
 
 def batch_workload(seed: int = 0):
@@ -377,8 +413,16 @@ def bench_hostcopy(args) -> dict:
         "render_ms": t_render / K * 1e3,
         "pcie_GBps": 12.0 * n * K / t_copy / 1e9,
         "host_memory_bytes": 12 * n + 4 * w * h + 8 * w * h * threads,
+        "Gpoints_per_s": n * K / elapsed / 1e9,
+        "device_memory_bytes": 12 * n + 4 * w * h,
         "device_path_frames_per_s": gpu_fps,
         "device_over_hostcopy": gpu_fps / fps,
+        "cpu": cpu_model(),
+        "paper": {"framerate_ratio": "up to 9x", "total_time_ratio": "up to 12x lower",
+                  "gpu_memory_ratio": "1.5x less",
+                  "hardware": "AMD Ryzen 7 3700X, 16 GB RAM; NVIDIA GeForce RTX 2070 SUPER 8 GB; "
+                              "CUDA 12.2; Vulkan 1.3.236; 1920x1080 at 144 Hz",
+                  "workload": "N and resolution not stated"},
     }
 
 
@@ -391,6 +435,9 @@ def main() -> int:
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--cpu-frames", type=int, default=48)
+    ap.add_argument("--dist", choices=["uniform", "mixture"], default="uniform",
+                    help="frame: uniform cube or mixture of 32 Gaussians (sigma 0.02)")
+    ap.add_argument("--footprint", type=int, choices=[1, 3], default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--splat", choices=["auto", "direct", "binned"], default="auto")
     ap.add_argument("--tile", type=int, default=0)
@@ -398,6 +445,8 @@ def main() -> int:
     ap.add_argument("--splits", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0, help="batched: persistent grid blocks")
     ap.add_argument("--bin-threads", type=int, default=0, help="threads per bin workgroup")
+    ap.add_argument("--piece-records", type=int, default=0,
+                    help="frame: records per balanced tile piece (0 auto or -1: static splits)")
     ap.add_argument("--autotune", action="store_true", help="time the shapes, keep the fastest")
     ap.add_argument("--hostcopy-frames", type=int, default=10, help="hostcopy: frames timed")
     ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy"],
@@ -448,21 +497,24 @@ def main() -> int:
         return 0
     n, w, h = 1 << args.log2n, args.width, args.height
     K, W = args.steps, args.warmup
-    pts = synth.uniform_cube(n, 0)
+    copy_ceiling = stream_copy_GBps()
+    pts = make_points(n, args.dist)
     dev = torch.from_numpy(pts).cuda()
     del pts
     cams = np.stack([synth.orbit_camera(f, w, h) for f in range(W + K)])
     stream = torch.cuda.current_stream()
     inst = mm.mm_create_instance(0, stream.cuda_stream)
     alloc = mm.mm_alloc_wrap(inst, dev.data_ptr(), dev.numel() * 4)
-    view = mm.mm_create_view(inst, mm.make_view_desc(alloc, n, 3, w, h, 1, 0, 0.001, False,
-                                                     cams[0]))
+    view = mm.mm_create_view(inst, mm.make_view_desc(alloc, n, 3, w, h, args.footprint, 0, 0.001,
+                                                     False, cams[0]))
     splat = {"auto": mm.MM_SPLAT_AUTO, "direct": mm.MM_SPLAT_DIRECT,
              "binned": mm.MM_SPLAT_BINNED}[args.splat]
     if args.autotune:
         mm.mm_autotune(view, 10)
-    elif splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits or args.bin_threads:
-        mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits, args.bin_threads)
+    elif (splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits or args.bin_threads
+          or args.piece_records):
+        pieces = mm.MM_PIECES_STATIC if args.piece_records < 0 else args.piece_records
+        mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits, args.bin_threads, pieces)
     tuning = mm.mm_get_tuning(view)
     mode = "direct" if tuning[0] == mm.MM_SPLAT_DIRECT else "binned"
     print(f"bench: {n} points, {w}x{h}, warmup {W}, timed {K}, splat {mode} {tuning}",
@@ -502,11 +554,12 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"3d-uniform-2^{args.log2n}pts-{w}x{h}-orbit-1deg",
-                   "points": n, "width": w, "height": h, "footprint": 1,
+        "config": {"workload": f"3d-{args.dist}-2^{args.log2n}pts-{w}x{h}-orbit-1deg"
+                               + (f"-{args.footprint}x{args.footprint}" if args.footprint != 1 else ""),
+                   "points": n, "width": w, "height": h, "footprint": args.footprint,
                    "amplitude": 0.001, "graph": "one hipGraph per frame",
                    "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2],
-                   "splits": tuning[3], "bin_threads": tuning[4]},
+                   "splits": tuning[3], "bin_threads": tuning[4], "piece_records": tuning[5]},
         "frames_per_s": K / elapsed,
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),
@@ -521,9 +574,10 @@ def main() -> int:
         "frame_roofline": {"bytes_per_frame": frame_bytes,
                            "achieved_GBps": frame_bytes / (elapsed / K) / 1e9,
                            "frac": frame_bytes / (elapsed / K) / 1e9 / HBM_PEAK_GBS},
+        "stream_copy_GBps": copy_ceiling,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, w, h, args.cpu_frames)
+        out["cpu_baseline"] = cpu_baseline(n, w, h, args.cpu_frames, args.dist, args.footprint)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -164,13 +164,20 @@ mm_status mm_read_frame(mm_view view, void* host_rgba, size_t bytes);
 typedef struct {
     uint32_t splat;             /* MM_SPLAT_* */
     uint32_t tile;              /* binned tile side: 16, 32 or 64 pixels; 0 = auto */
-    uint32_t points_per_thread; /* binned: 4, 8 or 16 (workgroup of 256 threads); 0 = auto */
+    uint32_t points_per_thread; /* binned: 4, 8 or 16 points per bin thread; 0 = auto */
     uint32_t splits;            /* binned: workgroups per tile in the depth test, 1, 2, 4
                                    or 8 (each takes a share of the points); 0 = auto */
     uint32_t bin_threads;       /* binned: threads of a bin workgroup, 256, 512 or 1024
                                    (a chunk is bin_threads * points_per_thread points);
                                    0 = auto */
+    uint32_t piece_records;     /* binned: 1024 .. 2^20 balances the depth test by
+                                   load: every tile is cut into pieces of about this
+                                   many records (at least points / 65535), taken by a
+                                   persistent grid; MM_PIECES_STATIC or 0 (auto):
+                                   `splits` workgroups per tile */
 } mm_tuning;
+
+#define MM_PIECES_STATIC 0xFFFFFFFFu
 
 /* Chooses the splat strategy and its shape for later frames; reallocates the
  * view's scratch buffers and rebuilds its graph. Synchronises. Returns
@@ -179,7 +186,9 @@ typedef struct {
  * bytes, exceeds 160 KiB). */
 mm_status mm_set_tuning(mm_view view, const mm_tuning* tuning);
 
-/* The resolved strategy and shape in use (never MM_SPLAT_AUTO or 0). */
+/* The resolved strategy and shape in use (never MM_SPLAT_AUTO; fields a
+ * strategy does not use are 0: splits when balanced by load, piece_records
+ * is MM_PIECES_STATIC with static splits). */
 mm_status mm_get_tuning(mm_view view, mm_tuning* out);
 
 /* Autotuning: times every supported strategy and shape on `frames` whole

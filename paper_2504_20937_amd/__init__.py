@@ -35,6 +35,7 @@ MM_FLOAT3 = 3
 MM_SPLAT_AUTO = 0
 MM_SPLAT_DIRECT = 1
 MM_SPLAT_BINNED = 2
+MM_PIECES_STATIC = 0xFFFFFFFF
 MM_DOMAIN_2D = 2
 MM_DOMAIN_3D = 3
 
@@ -67,7 +68,8 @@ class mm_view_desc(C.Structure):
 
 class mm_tuning(C.Structure):
     _fields_ = [("splat", C.c_uint32), ("tile", C.c_uint32), ("points_per_thread", C.c_uint32),
-                ("splits", C.c_uint32), ("bin_threads", C.c_uint32)]
+                ("splits", C.c_uint32), ("bin_threads", C.c_uint32),
+                ("piece_records", C.c_uint32)]
 
 
 class mm_cloud_desc(C.Structure):
@@ -286,23 +288,24 @@ def mm_destroy_view(view: int) -> None:
 
 
 def mm_set_tuning(view: int, splat: int = MM_SPLAT_AUTO, tile: int = 0,
-                  points_per_thread: int = 0, splits: int = 0, bin_threads: int = 0) -> None:
-    t = mm_tuning(splat, tile, points_per_thread, splits, bin_threads)
+                  points_per_thread: int = 0, splits: int = 0, bin_threads: int = 0,
+                  piece_records: int = 0) -> None:
+    t = mm_tuning(splat, tile, points_per_thread, splits, bin_threads, piece_records)
     _check(lib().mm_set_tuning(view, C.byref(t)), "mm_set_tuning")
 
 
-def mm_get_tuning(view: int) -> tuple[int, int, int, int, int]:
-    """(splat, tile, points_per_thread, splits, bin_threads) in use."""
+def mm_get_tuning(view: int) -> tuple[int, int, int, int, int, int]:
+    """(splat, tile, points_per_thread, splits, bin_threads, piece_records) in use."""
     t = mm_tuning()
     _check(lib().mm_get_tuning(view, C.byref(t)), "mm_get_tuning")
-    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads
+    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads, t.piece_records
 
 
-def mm_autotune(view: int, frames: int = 10) -> tuple[int, int, int, int, int]:
+def mm_autotune(view: int, frames: int = 10) -> tuple[int, int, int, int, int, int]:
     """Times the supported shapes, keeps the fastest; returns it as mm_get_tuning does."""
     t = mm_tuning()
     _check(lib().mm_autotune(view, frames, C.byref(t)), "mm_autotune")
-    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads
+    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads, t.piece_records
 
 
 def mm_set_camera(view: int, view_proj) -> None:

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -34,15 +35,34 @@ def sources() -> list[str]:
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
+def _spilling_kernels(remarks: str) -> list[str]:
+    """Kernels whose resource-usage remark reports per-lane scratch (register
+    spills or stack). The kernels are written to need none; a spill in a
+    1024-thread kernel is also a sign that its register budget is exceeded."""
+    bad, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > 0:
+            bad.append(f"{name} ({m.group(1)} B/lane)")
+    return bad
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(OUT, os.path.basename(src)[:-4] + ".o")
-    cmd = [hipcc(), *HIPFLAGS, "-c", src, "-o", obj]
+    cmd = [hipcc(), *HIPFLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError(f"hipcc failed on {src}")
+    bad = _spilling_kernels(r.stderr)
+    if bad:
+        raise RuntimeError(f"{os.path.basename(src)}: kernels use scratch: " + ", ".join(bad))
     return obj
 
 

@@ -66,7 +66,9 @@ struct TileView {
     uint32_t width, height;
     uint32_t tiles_x, tiles_y, ntiles;
     uint32_t num_wg;     // bin workgroups (chunks of points) of the view's cloud
-    uint32_t splits;     // tile-pass workgroups per tile
+    uint32_t splits;     // tile-pass workgroups per tile (static splits)
+    const uint32_t* piece_first;  // load-balanced: ntiles + 1 first partial block of
+                                  // each tile (nullptr: static splits)
     uint32_t full_clear; // 1: clear every tile not drawn this frame (the frame buffer
                          // holds no earlier frame); 0: only tiles drawn last frame
     uint32_t seed_lo, seed_hi;
@@ -85,7 +87,16 @@ struct TileArgs {
     TileView v;
     const uint32_t* stamp_in;
     uint32_t points_per_wg;
+    // load-balanced tile pass
+    uint32_t* tile_total;    // ntiles record counts (zero between frames)
+    uint32_t* piece_first;   // ntiles + 1 (the same array as v.piece_first)
+    uint2* items;            // work items: (tile, piece << 16 | pieces of the tile)
+    uint32_t* counters;      // [0] next item, [1] items this frame
+    uint32_t piece_records;  // records per piece
 };
+
+// Tiles the plan kernel handles in LDS (the bin pass allows no more).
+constexpr uint32_t kMaxPlanTiles = 4096;
 
 // Batched binned splat: many clouds, each with one or more views, in one
 // launch per pass. Work items are listed in device tables; a block takes
@@ -143,6 +154,11 @@ Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t threads, ui
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits);
 Launch merge_launch(int footprint, int shift, uint32_t ntiles);
 Launch seam_launch(int shift, uint32_t ntiles);
+// Load-balanced tile pass: count, plan, then a persistent grid of tile
+// workgroups over the work list.
+Launch count_launch(uint32_t ntiles, uint32_t num_wg);
+Launch plan_launch();
+Launch tile_list_launch(int footprint, int shift, uint32_t grid_blocks);
 
 // Batched binned splat. grid_blocks = 0 launches one block per item;
 // otherwise the launch is persistent, each block looping over items.

@@ -9,6 +9,7 @@
 // frame costs two host calls and no host synchronisation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -46,6 +47,11 @@ struct mm_view_s {
     uint64_t* part = nullptr;
     uint64_t* border = nullptr;
     uint64_t* apron = nullptr;
+    // load-balanced tile pass
+    uint32_t* tile_total = nullptr;
+    uint32_t* piece_first = nullptr;
+    uint2* items = nullptr;
+    uint32_t* counters = nullptr;
     uint32_t tiles_x = 0, tiles_y = 0, ntiles = 0, num_wg = 0, stamp = 0;
     // kernel arguments
     mm::PointArgs args{};
@@ -124,8 +130,14 @@ void free_splat_buffers(mm_view v) {
     for (void* p : {static_cast<void*>(v->depth), static_cast<void*>(v->seg),
                     static_cast<void*>(v->table), static_cast<void*>(v->active),
                     static_cast<void*>(v->part), static_cast<void*>(v->border),
-                    static_cast<void*>(v->apron)})
+                    static_cast<void*>(v->apron), static_cast<void*>(v->tile_total),
+                    static_cast<void*>(v->piece_first), static_cast<void*>(v->items),
+                    static_cast<void*>(v->counters)})
         if (p) (void)hipFree(p);
+    v->tile_total = nullptr;
+    v->piece_first = nullptr;
+    v->items = nullptr;
+    v->counters = nullptr;
     v->depth = nullptr;
     v->seg = nullptr;
     v->table = nullptr;
@@ -151,12 +163,24 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
         out.points_per_thread = 0;
         out.splits = 0;
         out.bin_threads = 0;
+        out.piece_records = 0;
         return MM_OK;
     }
     if (out.tile == 0) out.tile = tiles(32) <= 4096u ? 32u : 64u;
-    if (out.points_per_thread == 0) out.points_per_thread = 16;
-    if (out.bin_threads == 0) out.bin_threads = 256;
-    if (out.splits == 0) {
+    if (out.points_per_thread == 0) out.points_per_thread = 8;
+    if (out.bin_threads == 0) out.bin_threads = 1024;
+    // Auto is static splits: on the 1080p and 4K workloads the balanced
+    // pass's count and plan kernels cost more than the imbalance they remove.
+    if (out.piece_records == 0) out.piece_records = MM_PIECES_STATIC;
+    if (out.piece_records != MM_PIECES_STATIC) {
+        // balanced by load; a tile's piece count must fit 16 bits
+        if (out.piece_records < 1024 || out.piece_records > (1u << 20))
+            return fail(MM_ERR_INVALID_ARG, "tuning: piece_records %u outside [1024, 2^20]", out.piece_records);
+        if (static_cast<uint64_t>(out.piece_records) * 65535u < d.element_count)
+            return fail(MM_ERR_INVALID_ARG, "tuning: piece_records %u too small for %llu points",
+                        out.piece_records, (unsigned long long)d.element_count);
+        out.splits = 0;
+    } else if (out.splits == 0) {
         // enough workgroups per tile to spread the densest tiles over the
         // chip once the bin workgroups are many
         const uint64_t P = static_cast<uint64_t>(out.bin_threads) * out.points_per_thread;
@@ -164,7 +188,7 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
         out.splits = wgs >= 256 ? 2u : 1u;
     }
     if (!mm::binned_shape_ok(static_cast<int>(shift_of(out.tile)), static_cast<int>(out.points_per_thread),
-                             out.bin_threads, out.splits))
+                             out.bin_threads, out.splits == 0 ? 1u : out.splits))
         return fail(MM_ERR_INVALID_ARG,
                     "tuning: tile %u / points_per_thread %u / bin_threads %u / splits %u not in "
                     "{16,32,64} x {4,8,16} x {256,512,1024} x {1,2,4,8}",
@@ -212,8 +236,19 @@ mm_status setup_splat(mm_view v) {
         if (e == hipSuccess)
             e = hipMemsetAsync(v->active, 0, (static_cast<size_t>(v->ntiles) + 1) * 4, inst->stream);
         const uint64_t side_a = foot == 3 ? side + 2 : side;
-        if (e == hipSuccess)
-            e = alloc_n(&v->part, static_cast<uint64_t>(v->ntiles) * v->tuning.splits * side_a * side_a);
+        const bool balanced = v->tuning.piece_records != MM_PIECES_STATIC;
+        // balanced: every tile holds at most total / R + 1 pieces
+        const uint64_t blocks = balanced ? (d.element_count + v->tuning.piece_records - 1) /
+                                                   v->tuning.piece_records + v->ntiles
+                                         : static_cast<uint64_t>(v->ntiles) * v->tuning.splits;
+        if (e == hipSuccess) e = alloc_n(&v->part, blocks * side_a * side_a);
+        if (e == hipSuccess && balanced) {
+            e = alloc_n(&v->tile_total, v->ntiles);
+            if (e == hipSuccess) e = hipMemsetAsync(v->tile_total, 0, sizeof(uint32_t) * v->ntiles, inst->stream);
+            if (e == hipSuccess) e = alloc_n(&v->piece_first, static_cast<uint64_t>(v->ntiles) + 1);
+            if (e == hipSuccess) e = alloc_n(&v->items, blocks);
+            if (e == hipSuccess) e = alloc_n(&v->counters, 2);
+        }
         if (e == hipSuccess && foot == 3) {
             e = alloc_n(&v->border, static_cast<uint64_t>(v->ntiles) * 4 * side);
             if (e == hipSuccess) e = alloc_n(&v->apron, static_cast<uint64_t>(v->ntiles) * (4 * side + 4));
@@ -247,12 +282,29 @@ mm_status setup_splat(mm_view v) {
         t.v.ntiles = v->ntiles;
         t.v.num_wg = v->num_wg;
         t.v.splits = v->tuning.splits;
+        t.v.piece_first = v->piece_first;
         t.v.seed_lo = v->args.c.seed_lo;
         t.v.seed_hi = v->args.c.seed_hi;
         t.stamp_in = v->active + v->ntiles;
         t.points_per_wg = static_cast<uint32_t>(P);
+        t.tile_total = v->tile_total;
+        t.piece_first = v->piece_first;
+        t.items = v->items;
+        t.counters = v->counters;
+        t.piece_records = balanced ? v->tuning.piece_records : 0u;
         v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, nthreads, v->args.c.n, v->ntiles));
-        v->nodes.push_back(mm::tile_launch(foot, static_cast<int>(shift), v->ntiles, v->tuning.splits));
+        if (balanced) {
+            int cus = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, inst->device) != hipSuccess ||
+                cus <= 0)
+                cus = 256;
+            const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(blocks, 2ull * cus));
+            v->nodes.push_back(mm::count_launch(v->ntiles, v->num_wg));
+            v->nodes.push_back(mm::plan_launch());
+            v->nodes.push_back(mm::tile_list_launch(foot, static_cast<int>(shift), grid));
+        } else {
+            v->nodes.push_back(mm::tile_launch(foot, static_cast<int>(shift), v->ntiles, v->tuning.splits));
+        }
         v->nodes.push_back(mm::merge_launch(foot, static_cast<int>(shift), v->ntiles));
         if (foot == 3) v->nodes.push_back(mm::seam_launch(static_cast<int>(shift), v->ntiles));
     }
@@ -495,7 +547,7 @@ mm_status mm_create_view(mm_instance inst, const mm_view_desc* desc, mm_view* ou
         return fail(MM_ERR_INVALID_ARG, "create_view: position is not an alloc of this instance");
     MM_TRY(validate_desc(inst, desc));
     mm_tuning tuning{};
-    MM_TRY(resolve_tuning(*desc, mm_tuning{MM_SPLAT_AUTO, 0, 0, 0, 0}, tuning));
+    MM_TRY(resolve_tuning(*desc, mm_tuning{MM_SPLAT_AUTO, 0, 0, 0, 0, 0}, tuning));
     DeviceGuard guard(inst->device);
     mm_view v = new (std::nothrow) mm_view_s();
     if (!v) return fail(MM_ERR_OUT_OF_MEMORY, "create_view: host allocation");
@@ -554,21 +606,24 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     char key[256];
     std::snprintf(key, sizeof key, "view:%s:d%d:n%llu:%ux%u:f%u", device_arch(inst->device).c_str(),
                   (int)d.domain, (unsigned long long)d.element_count, d.width, d.height, d.footprint);
-    uint32_t cached[5];
+    uint32_t cached[kTuneValues];
     if (tune_cache_lookup(key, cached)) {
-        const mm_tuning t{cached[0], cached[1], cached[2], cached[3], cached[4]};
+        const mm_tuning t{cached[0], cached[1], cached[2], cached[3], cached[4], cached[5]};
         if (mm_set_tuning(v, &t) == MM_OK) return mm_get_tuning(v, out);
     }
     const size_t bytes = static_cast<size_t>(d.element_count) * 4u * static_cast<size_t>(d.format);
     void* saved = nullptr;
     MM_HIP(hipMalloc(&saved, bytes));
     hipError_t e = hipMemcpyAsync(saved, v->position->ptr, bytes, hipMemcpyDeviceToDevice, inst->stream);
-    std::vector<mm_tuning> cands = {{MM_SPLAT_DIRECT, 0, 0, 0, 0}};
+    std::vector<mm_tuning> cands = {{MM_SPLAT_DIRECT, 0, 0, 0, 0, 0}};
     for (uint32_t tile : {32u, 64u})
-        for (uint32_t threads : {256u, 512u, 1024u})
-            for (uint32_t ppt : {8u, 16u})
-                for (uint32_t splits : {1u, 2u, 4u})
-                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, splits, threads});
+        for (uint32_t threads : {256u, 1024u})
+            for (uint32_t ppt : {8u, 16u}) {
+                for (uint32_t pieces : {0u, 4096u, 16384u})
+                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, 0, threads, pieces});
+                for (uint32_t splits : {1u, 2u})
+                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, splits, threads, MM_PIECES_STATIC});
+            }
     mm_tuning best{};
     float best_ms = 0.0f;
     for (const mm_tuning& c : cands) {
@@ -589,8 +644,8 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     if (se != hipSuccess) return hip_fail(se, "autotune: synchronising");
     if (best_ms == 0.0f) return fail(MM_ERR_HIP, "autotune: no candidate ran");
     MM_TRY(mm_set_tuning(v, &best));
-    const uint32_t vals[5] = {best.splat, best.tile, best.points_per_thread, best.splits,
-                              best.bin_threads};
+    const uint32_t vals[kTuneValues] = {best.splat, best.tile, best.points_per_thread, best.splits,
+                                        best.bin_threads, best.piece_records};
     tune_cache_store(key, vals);
     return mm_get_tuning(v, out);
 }

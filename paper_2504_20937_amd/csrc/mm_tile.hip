@@ -85,22 +85,21 @@ struct TileShape {
     static constexpr uint32_t kCol = 4096;  // bin workgroups per pass over the column
 };
 
-// Split z of tile t: the per-pixel minimum over the records of bin workgroups
-// [num_wg * z / splits, num_wg * (z + 1) / splits), written as partial keys.
-// 1024 threads; keys (A * A) and col (kCol) are LDS. Ends with the block
-// synchronised.
+// Tile t over bin workgroups [w_lo, w_hi): the per-pixel minimum of their
+// records, written as partial key block `piece` of v.part. 1024 threads; keys
+// (A * A) and col (kCol) are LDS. Ends with the block synchronised.
 template <int FOOT, int SHIFT>
-__device__ __forceinline__ void tile_split(const TileView& v, uint32_t t, uint32_t z, uint32_t P,
+__device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32_t w_lo,
+                                           uint32_t w_hi, uint32_t piece, uint32_t P,
                                            uint64_t* keys, uint32_t* col) {
     using Sh = TileShape<FOOT, SHIFT>;
     constexpr uint32_t S = Sh::S, A = Sh::A, kCol = Sh::kCol;
-    constexpr uint32_t kGroup = S;     // lanes reading one chunk
+    constexpr uint32_t kGroup = 16;    // lanes reading one chunk (records per chunk and
+                                       // tile are about P / active tiles)
     constexpr uint32_t kGroups = 1024u / kGroup;
     constexpr uint32_t kInFlight = 16; // chunks per lane group per round
     constexpr uint32_t kPieces = 2;    // records per lane per chunk per round
     const uint32_t tid = threadIdx.x;
-    const uint32_t w_lo = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * z / v.splits);
-    const uint32_t w_hi = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * (z + 1) / v.splits);
     for (uint32_t q = tid; q < A * A; q += 1024u) keys[q] = kEmptyKey;
     const uint32_t group = tid / kGroup, sub = tid % kGroup;
     const uint32_t stride = v.ntiles + 1u;
@@ -108,17 +107,15 @@ __device__ __forceinline__ void tile_split(const TileView& v, uint32_t t, uint32
     for (uint32_t base = w_lo; base < w_hi; base += kCol) {
         const uint32_t nb = min(kCol, w_hi - base);
         __syncthreads();  // keys initialised / previous pass done with col
+        // Branch-free: lanes past the column's end read its last row (unused),
+        // so all of a lane's table loads are in flight together.
         uint32_t cs[kCol / 1024], ce[kCol / 1024];
 #pragma unroll
         for (uint32_t k = 0; k < kCol / 1024; ++k) {
-            const uint32_t c = tid + k * 1024u;
-            cs[k] = 0;
-            ce[k] = 0;
-            if (c < nb) {
-                const uint16_t* row = v.table + static_cast<uint64_t>(base + c) * stride;
-                cs[k] = row[t];
-                ce[k] = row[t + 1];
-            }
+            const uint32_t c = min(tid + k * 1024u, nb - 1u);
+            const uint16_t* row = v.table + static_cast<uint64_t>(base + c) * stride;
+            cs[k] = row[t];
+            ce[k] = row[t + 1];
         }
 #pragma unroll
         for (uint32_t k = 0; k < kCol / 1024; ++k) {
@@ -167,9 +164,19 @@ __device__ __forceinline__ void tile_split(const TileView& v, uint32_t t, uint32
         }
     }
     __syncthreads();
-    uint64_t* part = v.part + (static_cast<uint64_t>(t) * v.splits + z) * (A * A);
+    uint64_t* part = v.part + static_cast<uint64_t>(piece) * (A * A);
     for (uint32_t q = tid; q < A * A; q += 1024u) part[q] = keys[q];
     __syncthreads();
+}
+
+// Split z of tile t: bin workgroups [num_wg * z / splits, num_wg * (z + 1) /
+// splits), partial block t * splits + z.
+template <int FOOT, int SHIFT>
+__device__ __forceinline__ void tile_split(const TileView& v, uint32_t t, uint32_t z, uint32_t P,
+                                           uint64_t* keys, uint32_t* col) {
+    const uint32_t w_lo = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * z / v.splits);
+    const uint32_t w_hi = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * (z + 1) / v.splits);
+    tile_range<FOOT, SHIFT>(v, t, w_lo, w_hi, t * v.splits + z, P, keys, col);
 }
 
 template <int FOOT, int SHIFT>
@@ -182,6 +189,117 @@ __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
     if (t >= a.v.ntiles) return;
     if (tile_flag(a.v, t) != *a.stamp_in) return;  // nothing to draw
     tile_split<FOOT, SHIFT>(a.v, t, z, a.points_per_wg, keys, col);
+}
+
+// Load-balanced tile pass. Per tile, the count kernel sums the records over
+// all bin workgroups; the plan kernel cuts every tile into pieces of about
+// piece_records records (ranges of bin workgroups of equal length), lays the
+// pieces out tile by tile (piece_first) and lists them as work items; a
+// persistent grid of tile workgroups takes items from a counter, so dense
+// tiles spread over many CUs and no workgroup is launched for an empty tile.
+
+// Grid (ceil(ntiles / 64), row groups), 64 threads: thread t sums its tile's
+// counts over a range of table rows (64 consecutive tiles read one 128-byte
+// line of each row), then adds them to the tile's total.
+__global__ __launch_bounds__(64) void count_kernel(TileArgs a) {
+    const uint32_t t = blockIdx.x * 64u + threadIdx.x;
+    if (t >= a.v.ntiles) return;
+    const uint32_t rows = (a.v.num_wg + gridDim.y - 1) / gridDim.y;
+    const uint32_t r0 = blockIdx.y * rows, r1 = min(a.v.num_wg, r0 + rows);
+    const uint32_t stride = a.v.ntiles + 1u;
+    uint32_t sum = 0;
+    uint32_t r = r0;
+    for (; r + 8 <= r1; r += 8) {
+        uint32_t s0[8], s1[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            const uint16_t* row = a.v.table + static_cast<uint64_t>(r + k) * stride;
+            s0[k] = row[t];
+            s1[k] = row[t + 1];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) sum += s1[k] - s0[k];
+    }
+    for (; r < r1; ++r) {
+        const uint16_t* row = a.v.table + static_cast<uint64_t>(r) * stride;
+        sum += static_cast<uint32_t>(row[t + 1]) - row[t];
+    }
+    if (sum) atomicAdd(&a.tile_total[t], sum);
+}
+
+// One workgroup of 1024 threads: pieces per tile, their exclusive scan
+// (piece_first), the work items, the item count; resets the work counter and
+// the tile totals for the next frame.
+__global__ __launch_bounds__(1024) void plan_kernel(TileArgs a) {
+    __shared__ uint32_t pieces[kMaxPlanTiles + 1];
+    __shared__ uint32_t wave_sum[16];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t nt = a.v.ntiles;
+    for (uint32_t t = tid; t < nt; t += 1024u) {
+        const uint32_t total = a.tile_total[t];
+        pieces[t] = (total + a.piece_records - 1) / a.piece_records;
+        a.tile_total[t] = 0u;
+    }
+    __syncthreads();
+    // exclusive scan of pieces[0..nt): each wave a contiguous run of 64-blocks
+    const uint32_t nblk = (nt + 63u) / 64u, per = (nblk + 15u) / 16u;
+    const uint32_t b0 = min(nblk, wave * per), b1 = min(nblk, b0 + per);
+    uint32_t lsum = 0;
+    for (uint32_t b = b0; b < b1; ++b) lsum += b * 64u + lane < nt ? pieces[b * 64u + lane] : 0u;
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t u = __shfl_up(lsum, d, 64);
+        if (lane >= d) lsum += u;
+    }
+    if (lane == 63) wave_sum[wave] = lsum;
+    __syncthreads();
+    uint32_t carry = 0, total = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+        carry += w < wave ? wave_sum[w] : 0u;
+        total += wave_sum[w];
+    }
+    for (uint32_t b = b0; b < b1; ++b) {
+        const uint32_t i = b * 64u + lane;
+        const uint32_t v = i < nt ? pieces[i] : 0u;
+        uint32_t inc = v;
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint32_t u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
+        }
+        if (i < nt) {
+            const uint32_t first = carry + inc - v;
+            a.piece_first[i] = first;
+            for (uint32_t j = 0; j < v; ++j) a.items[first + j] = make_uint2(i, (j << 16) | v);
+        }
+        carry += __shfl(inc, 63, 64);
+    }
+    if (tid == 0) {
+        a.piece_first[nt] = total;
+        a.counters[0] = 0u;      // next item to take
+        a.counters[1] = total;   // items this frame
+    }
+}
+
+// Persistent grid: each workgroup takes items (tile, piece j of k) until the
+// list is done; piece j covers bin workgroups [num_wg * j / k, num_wg * (j + 1) / k).
+template <int FOOT, int SHIFT>
+__global__ __launch_bounds__(1024) void tile_list_kernel(TileArgs a) {
+    using Sh = TileShape<FOOT, SHIFT>;
+    __shared__ uint64_t keys[Sh::A * Sh::A];
+    __shared__ uint32_t col[Sh::kCol];
+    __shared__ uint32_t next;
+    const uint32_t n_items = __hip_atomic_load(&a.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        if (threadIdx.x == 0) next = atomicAdd(&a.counters[0], 1u);
+        __syncthreads();
+        const uint32_t it = next;
+        __syncthreads();  // every thread has read `next` before it is written again
+        if (it >= n_items) break;
+        const uint2 item = a.items[it];
+        const uint32_t t = item.x, j = item.y >> 16, k = item.y & 0xFFFFu;
+        const uint32_t w_lo = static_cast<uint32_t>(static_cast<uint64_t>(a.v.num_wg) * j / k);
+        const uint32_t w_hi = static_cast<uint32_t>(static_cast<uint64_t>(a.v.num_wg) * (j + 1) / k);
+        tile_range<FOOT, SHIFT>(a.v, t, w_lo, w_hi, a.v.piece_first[t] + j, a.points_per_wg, keys, col);
+    }
 }
 
 template <int FOOT, int SHIFT>
@@ -223,10 +341,23 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
         }
         return;
     }
-    const uint64_t* part = v.part + static_cast<uint64_t>(t) * v.splits * (A * A);
+    // the tile's partial blocks: its pieces, or its `splits` static splits
+    const uint32_t first = v.piece_first ? v.piece_first[t] : t * v.splits;
+    const uint32_t count = v.piece_first ? v.piece_first[t + 1] - first : v.splits;
+    const uint64_t* part = v.part + static_cast<uint64_t>(first) * (A * A);
+    // eight partial blocks per round in flight: a tile balanced by load can
+    // have tens of pieces
     auto key_at = [&](uint32_t q) {
-        uint64_t k = part[q];
-        for (uint32_t z = 1; z < v.splits; ++z) {
+        uint64_t k = kEmptyKey;
+        uint32_t z = 0;
+        for (; z + 8 <= count; z += 8) {
+            uint64_t p[8];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) p[u] = part[static_cast<uint64_t>(z + u) * (A * A) + q];
+#pragma unroll
+            for (uint32_t u = 0; u < 8; ++u) k = p[u] < k ? p[u] : k;
+        }
+        for (; z < count; ++z) {
             const uint64_t p = part[static_cast<uint64_t>(z) * (A * A) + q];
             k = p < k ? p : k;
         }
@@ -427,6 +558,43 @@ Launch seam_launch(int shift, uint32_t ntiles) {
     l.func = pick_seam(shift, false);
     l.block = dim3(256);
     l.grid = dim3(ntiles);
+    l.shared = 0;
+    return l;
+}
+
+Launch count_launch(uint32_t ntiles, uint32_t num_wg) {
+    Launch l;
+    l.func = reinterpret_cast<const void*>(&count_kernel);
+    l.block = dim3(64);
+    // about 64 table rows per workgroup
+    l.grid = dim3((ntiles + 63u) / 64u, max(1u, min(64u, (num_wg + 63u) / 64u)));
+    l.shared = 0;
+    return l;
+}
+
+Launch plan_launch() {
+    Launch l;
+    l.func = reinterpret_cast<const void*>(&plan_kernel);
+    l.block = dim3(1024);
+    l.grid = dim3(1);
+    l.shared = 0;
+    return l;
+}
+
+template <int FOOT>
+const void* pick_tile_list(int shift) {
+    switch (shift) {
+        case 4: return reinterpret_cast<const void*>(&tile_list_kernel<FOOT, 4>);
+        case 5: return reinterpret_cast<const void*>(&tile_list_kernel<FOOT, 5>);
+        default: return reinterpret_cast<const void*>(&tile_list_kernel<FOOT, 6>);
+    }
+}
+
+Launch tile_list_launch(int footprint, int shift, uint32_t grid_blocks) {
+    Launch l;
+    l.func = footprint == 3 ? pick_tile_list<3>(shift) : pick_tile_list<1>(shift);
+    l.block = dim3(1024);
+    l.grid = dim3(grid_blocks);
     l.shared = 0;
     return l;
 }

@@ -27,16 +27,22 @@ def rig(torch_gpu):
     r.close()
 
 
-# splat strategies and shapes: (splat, tile, points_per_thread, splits, bin_threads); 0 = auto
-DIRECT = (1, 0, 0, 0, 0)
-BINNED = (2, 0, 0, 0, 0)
+# splat strategies and shapes: (splat, tile, points_per_thread, splits, bin_threads,
+# piece_records); 0 = auto. piece_records 1024 .. 2^20 balances the depth test by
+# load; MM_PIECES_STATIC (and auto) gives `splits` workgroups per tile.
+ST = 0xFFFFFFFF
+DIRECT = (1, 0, 0, 0, 0, 0)
+BINNED = (2, 0, 0, 0, 0, 0)
 MODES = [DIRECT, BINNED]
-SHAPES = [DIRECT, (2, 16, 4, 1, 256), (2, 32, 8, 4, 256), (2, 64, 16, 2, 256), (2, 32, 4, 8, 256),
-          (2, 32, 16, 2, 512), (2, 32, 16, 1, 1024), (2, 64, 8, 4, 1024), (2, 16, 4, 2, 512)]
+SHAPES = [DIRECT, (2, 16, 4, 1, 256, ST), (2, 32, 8, 4, 256, ST), (2, 64, 16, 2, 256, ST),
+          (2, 32, 4, 8, 256, ST), (2, 32, 16, 2, 512, ST), (2, 32, 16, 0, 1024, 1024),
+          (2, 64, 8, 0, 1024, 8192), (2, 16, 4, 0, 512, 2048), (2, 32, 8, 0, 256, 4096)]
 
 
 def _ids(modes):
-    return ["direct" if m[0] == 1 else f"binned-t{m[1]}-p{m[2]}-z{m[3]}-n{m[4]}" for m in modes]
+    return ["direct" if m[0] == 1 else
+            f"binned-t{m[1]}-p{m[2]}-n{m[4]}-" + (f"z{m[3]}" if m[5] == ST else f"r{m[5]}")
+            for m in modes]
 
 
 def _run(rig, pts, dim, w, h, foot, seed, amp, wrap, frames, cam_fn, check_every=1,
@@ -319,14 +325,15 @@ def test_tuning_choices_and_validation(rig):
     dev, alloc = rig.cloud(pts)
     cam = synth.orbit_camera(0, 1920, 1080)
     view = rig.view(alloc, 5000, 3, 1920, 1080, 1, 0, 0.001, False, cam)
-    # 5000 points: 2 bin workgroups
-    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 16, 1, 256)
-    for bad, status in [((2, 128, 16, 0, 0), mm.MM_ERR_INVALID_ARG),
-                        ((2, 32, 3, 0, 0), mm.MM_ERR_INVALID_ARG),
-                        ((2, 32, 16, 3, 0), mm.MM_ERR_INVALID_ARG),
-                        ((2, 32, 16, 0, 384), mm.MM_ERR_INVALID_ARG),
-                        ((7, 0, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
-                        ((2, 16, 16, 0, 0), mm.MM_ERR_UNSUPPORTED)]:
+    # 5000 points: one bin workgroup, so one workgroup per tile in the depth test
+    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST)
+    for bad, status in [((2, 128, 16, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
+                        ((2, 32, 3, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
+                        ((2, 32, 16, 3, 0, ST), mm.MM_ERR_INVALID_ARG),
+                        ((2, 32, 16, 0, 384, 0), mm.MM_ERR_INVALID_ARG),
+                        ((2, 32, 16, 0, 256, 512), mm.MM_ERR_INVALID_ARG),
+                        ((7, 0, 0, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
+                        ((2, 16, 16, 0, 0, 0), mm.MM_ERR_UNSUPPORTED)]:
         with pytest.raises(mm.MMError) as e:
             mm.mm_set_tuning(view, *bad)
         assert e.value.status == status, (bad, str(e.value))
@@ -335,13 +342,13 @@ def test_tuning_choices_and_validation(rig):
     ref = pts.copy()
     assert np.array_equal(mm.mm_read_frame(view, 1920, 1080),
                           oracle.step_render(ref, 0, 0, 0.001, False, cam, 1920, 1080, 1))
-    mm.mm_set_tuning(view, 2, 64, 4, 8, 512)
-    assert mm.mm_get_tuning(view) == (2, 64, 4, 8, 512)
+    mm.mm_set_tuning(view, 2, 64, 4, 8, 512, ST)
+    assert mm.mm_get_tuning(view) == (2, 64, 4, 8, 512, ST)
     mm.mm_step_render(view, 1)
     assert np.array_equal(mm.mm_read_frame(view, 1920, 1080),
                           oracle.step_render(ref, 0, 1, 0.001, False, cam, 1920, 1080, 1))
-    mm.mm_set_tuning(view, 1, 0, 0, 0, 0)
-    assert mm.mm_get_tuning(view) == (1, 0, 0, 0, 0)
+    mm.mm_set_tuning(view, 1, 0, 0, 0, 0, 0)
+    assert mm.mm_get_tuning(view) == (1, 0, 0, 0, 0, 0)
 
 
 def test_largest_screen_falls_back_to_direct(rig):
