@@ -63,18 +63,43 @@ __device__ __forceinline__ uint32_t tile_flag(const TileView& v, uint32_t t) {
     return load_flag(&v.active[t]);
 }
 
-template <int FOOT, uint32_t S, uint32_t A>
+// The record's key into its centre pixel of the tile (S x S keys in LDS).
+// A 3x3 footprint is applied afterwards, by a 3x3 minimum over the centre
+// minima (exact: a pixel's key is the minimum over the records centred in
+// its neighbourhood, in any grouping), so every record costs one LDS atomic
+// whatever the footprint.
+template <uint32_t S>
 __device__ __forceinline__ void splat_record(uint64_t* keys, uint64_t r, uint32_t gbase) {
     const uint32_t lo = static_cast<uint32_t>(r);
     const uint32_t cx = lo & 0xFFu, cy = (lo >> 8) & 0xFFu;
     const uint64_t key = (r & 0xFFFFFFFF00000000ull) | static_cast<uint64_t>(gbase + (lo >> 16));
+    atomic_min_lds(&keys[cy * S + cx], key);
+}
+
+// Partial key block (A x A) of the tile from its centre minima: with the 3x3
+// footprint, block entry (i, j) is pixel (j - 1, i - 1) of the tile and takes
+// the minimum over centres (cx, cy) in [j - 2, j] x [i - 2, i] inside the tile.
+template <int FOOT, uint32_t S, uint32_t A>
+__device__ __forceinline__ void write_part(const uint64_t* keys, uint64_t* part) {
+    const uint32_t tid = threadIdx.x;
     if constexpr (FOOT == 1) {
-        atomic_min_lds(&keys[cy * S + cx], key);
+        for (uint32_t q = tid; q < S * S; q += 1024u) part[q] = keys[q];
     } else {
+        for (uint32_t q = tid; q < A * A; q += 1024u) {
+            const uint32_t i = q / A, j = q % A;
+            uint64_t m = kEmptyKey;
 #pragma unroll
-        for (uint32_t dy = 0; dy < 3; ++dy)
+            for (uint32_t dy = 0; dy < 3; ++dy) {
+                const uint32_t cy = i - dy;  // wraps past 0: rejected below
+                if (cy >= S) continue;
 #pragma unroll
-            for (uint32_t dx = 0; dx < 3; ++dx) atomic_min_lds(&keys[(cy + dy) * A + cx + dx], key);
+                for (uint32_t dx = 0; dx < 3; ++dx) {
+                    const uint32_t cx = j - dx;
+                    if (cx < S) m = min(m, keys[cy * S + cx]);
+                }
+            }
+            part[q] = m;
+        }
     }
 }
 
@@ -83,89 +108,162 @@ struct TileShape {
     static constexpr uint32_t S = 1u << SHIFT;
     static constexpr uint32_t A = FOOT == 3 ? S + 2 : S;
     static constexpr uint32_t kCol = 4096;  // bin workgroups per pass over the column
+    // LDS words beside the keys: run offsets (kCol + 1), run locations (kCol),
+    // one 64-word window mark per wave, and the scan's wave sums (2 x 16)
+    static constexpr uint32_t kColLds = (kCol + 1) + kCol + 16 * 64 + 32;
 };
+
+// Inclusive scan of two values over the 64 lanes of a wave.
+__device__ __forceinline__ void wave_scan2(uint32_t& a, uint32_t& b, uint32_t lane) {
+#pragma unroll
+    for (uint32_t d = 1; d < 64; d <<= 1) {
+        const uint32_t ua = __shfl_up(a, d, 64), ub = __shfl_up(b, d, 64);
+        if (lane >= d) {
+            a += ua;
+            b += ub;
+        }
+    }
+}
+
+// Records [r0, r1) of the flat record list of one pass (the concatenation of
+// the tile's non-empty runs, run k holding records [roff[k], roff[k + 1])
+// from chunk base + (rloc[k] >> 16) at offset rloc[k] & 0xFFFF), splatted by
+// one wave. The wave takes 64 consecutive records per step, one per lane: a
+// lane finds its run from the run starts that fall inside the step's window
+// (marked in the wave's LDS mark words, gathered with a ballot, counted with
+// mbcnt), so every load of a step is contiguous and no lane waits on a
+// per-run branch. U steps are loaded before their records are splatted.
+template <uint32_t S, uint32_t U>
+__device__ __forceinline__ void splat_flat(const uint64_t* seg, uint32_t gbase0, uint32_t P,
+                                           uint64_t* keys, const uint32_t* roff,
+                                           const uint32_t* rloc, uint32_t nruns, uint32_t r0,
+                                           uint32_t r1, uint32_t* mark) {
+    const uint32_t lane = threadIdx.x & 63u;
+    mark[lane] = 0xFFFFFFFFu;  // no window starts there
+    // run k holding record r0: roff[k] <= r0 < roff[k + 1] (roff[nruns] = total > r0)
+    uint32_t lo = 0, hi = nruns;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (roff[mid] <= r0) lo = mid;
+        else hi = mid;
+    }
+    uint32_t k = lo;
+    for (uint32_t w0 = r0; w0 < r1; w0 += 64u * U) {
+        uint64_t r[U];
+        uint32_t gb[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t w = w0 + 64u * u;  // window [w, w + 64)
+            // lane j holds the start of run k + 1 + j; they are increasing, the
+            // first lies past w, and at most 64 of them fall inside (w, w + 64]
+            const uint32_t b = roff[min(k + 1u + lane, nruns)];
+            const uint32_t pos = b - w;
+            if (pos < 64u) mark[pos] = w;
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t starts = __ballot(mark[lane] == w);
+            const uint32_t crossed = static_cast<uint32_t>(__popcll(starts)) + (__ballot(pos == 64u) != 0);
+            // runs started at or before this lane's record
+            const uint32_t upto = __builtin_amdgcn_mbcnt_hi(
+                static_cast<uint32_t>(starts >> 32),
+                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(starts), 0u)) +
+                static_cast<uint32_t>((starts >> lane) & 1ull);
+            const uint32_t f = w + lane;
+            const uint32_t kl = min(k + upto, nruns - 1u);
+            const uint32_t loc = rloc[kl], st = roff[kl];
+            const uint32_t off = (loc >> 16) * P + (loc & 0xFFFFu) + (f < r1 ? f - st : 0u);
+            r[u] = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(seg) +
+                                                      (static_cast<uint64_t>(off) << 3));
+            gb[u] = gbase0 + (loc >> 16) * P;
+            k += crossed;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            if (w0 + 64u * u + lane < r1) splat_record<S>(keys, r[u], gb[u]);
+    }
+}
 
 // Tile t over bin workgroups [w_lo, w_hi): the per-pixel minimum of their
 // records, written as partial key block `piece` of v.part. 1024 threads; keys
-// (A * A) and col (kCol) are LDS. Ends with the block synchronised.
+// (S * S centre minima) and lds (kColLds words) are LDS. Ends with the block
+// synchronised.
+//
+// Per pass over up to kCol bin workgroups: each thread reads the (start,
+// end) pairs of 4 consecutive workgroups from the table, a block scan over
+// the non-empty runs gives their flat offsets (roff) and compacted locations
+// (rloc), and the flat record list is cut into 16 equal ranges, one per wave.
+// A wave's work thus depends on the records, not on how they fall into runs.
 template <int FOOT, int SHIFT>
 __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32_t w_lo,
                                            uint32_t w_hi, uint32_t piece, uint32_t P,
-                                           uint64_t* keys, uint32_t* col) {
+                                           uint64_t* keys, uint32_t* lds) {
     using Sh = TileShape<FOOT, SHIFT>;
     constexpr uint32_t S = Sh::S, A = Sh::A, kCol = Sh::kCol;
-    constexpr uint32_t kGroup = 16;    // lanes reading one chunk (records per chunk and
-                                       // tile are about P / active tiles)
-    constexpr uint32_t kGroups = 1024u / kGroup;
-    constexpr uint32_t kInFlight = 16; // chunks per lane group per round
-    constexpr uint32_t kPieces = 2;    // records per lane per chunk per round
-    const uint32_t tid = threadIdx.x;
-    for (uint32_t q = tid; q < A * A; q += 1024u) keys[q] = kEmptyKey;
-    const uint32_t group = tid / kGroup, sub = tid % kGroup;
+    constexpr uint32_t kPer = kCol / 1024u;  // bin workgroups per thread and pass
+    uint32_t* roff = lds;
+    uint32_t* rloc = roff + kCol + 1;
+    uint32_t* marks = rloc + kCol;
+    uint32_t* wsum = marks + 16 * 64;  // [0, 16): counts, [16, 32): runs
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    uint32_t* mark = marks + wave * 64u;
+    for (uint32_t q = tid; q < S * S; q += 1024u) keys[q] = kEmptyKey;
     const uint32_t stride = v.ntiles + 1u;
 
     for (uint32_t base = w_lo; base < w_hi; base += kCol) {
         const uint32_t nb = min(kCol, w_hi - base);
-        __syncthreads();  // keys initialised / previous pass done with col
-        // Branch-free: lanes past the column's end read its last row (unused),
-        // so all of a lane's table loads are in flight together.
-        uint32_t cs[kCol / 1024], ce[kCol / 1024];
+        __syncthreads();  // keys initialised / previous pass done with roff, rloc
+        // Branch-free: lanes past the column's end read its last row (count
+        // forced to 0), so all of a lane's table loads are in flight together.
+        uint32_t cs[kPer], cn[kPer];
 #pragma unroll
-        for (uint32_t k = 0; k < kCol / 1024; ++k) {
-            const uint32_t c = min(tid + k * 1024u, nb - 1u);
-            const uint16_t* row = v.table + static_cast<uint64_t>(base + c) * stride;
+        for (uint32_t k = 0; k < kPer; ++k) {
+            const uint32_t c = tid * kPer + k;
+            const uint16_t* row = v.table + static_cast<uint64_t>(base + min(c, nb - 1u)) * stride;
             cs[k] = row[t];
-            ce[k] = row[t + 1];
+            cn[k] = row[t + 1];
         }
+        uint32_t tc = 0, tr = 0;  // this thread's records and non-empty runs
 #pragma unroll
-        for (uint32_t k = 0; k < kCol / 1024; ++k) {
-            const uint32_t c = tid + k * 1024u;
-            if (c < nb) col[c] = (cs[k] << 16) | (ce[k] - cs[k]);
+        for (uint32_t k = 0; k < kPer; ++k) {
+            cn[k] = tid * kPer + k < nb ? cn[k] - cs[k] : 0u;
+            tc += cn[k];
+            tr += cn[k] != 0u;
+        }
+        uint32_t ic = tc, ir = tr;
+        wave_scan2(ic, ir, lane);
+        if (lane == 63u) {
+            wsum[wave] = ic;
+            wsum[16 + wave] = ir;
         }
         __syncthreads();
-        for (uint32_t c0 = group; c0 < nb; c0 += kGroups * kInFlight) {
-            uint64_t r[kInFlight][kPieces];
-            uint32_t cv[kInFlight];  // start << 16 | count of chunk c0 + u * kGroups
+        uint32_t total = 0, nruns = 0, oc = ic - tc, orr = ir - tr;
 #pragma unroll
-            for (uint32_t u = 0; u < kInFlight; ++u) {
-                const uint32_t c = c0 + u * kGroups;
-                cv[u] = c < nb ? col[c] : 0u;
-                const uint64_t* src = v.seg + static_cast<uint64_t>(base + c) * P + (cv[u] >> 16);
+        for (uint32_t w = 0; w < 16; ++w) {
+            const uint32_t c = wsum[w], r = wsum[16 + w];
+            total += c;
+            nruns += r;
+            oc += w < wave ? c : 0u;
+            orr += w < wave ? r : 0u;
+        }
 #pragma unroll
-                for (uint32_t p = 0; p < kPieces; ++p) {
-                    const uint32_t j = sub + p * kGroup;
-                    r[u][p] = j < (cv[u] & 0xFFFFu) ? src[j] : 0ull;
-                }
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kInFlight; ++u) {
-                const uint32_t gbase = (base + c0 + u * kGroups) * P;
-#pragma unroll
-                for (uint32_t p = 0; p < kPieces; ++p)
-                    if (sub + p * kGroup < (cv[u] & 0xFFFFu))
-                        splat_record<FOOT, S, A>(keys, r[u][p], gbase);
-            }
-            // the rest of chunks longer than kPieces * kGroup records
-#pragma unroll 1
-            for (uint32_t u = 0; u < kInFlight; ++u) {
-                const uint32_t cnt = cv[u] & 0xFFFFu;
-                if (cnt <= kPieces * kGroup) continue;
-                const uint32_t gbase = (base + c0 + u * kGroups) * P;
-                const uint64_t* src = v.seg + static_cast<uint64_t>(gbase) + (cv[u] >> 16);
-                for (uint32_t j = kPieces * kGroup + sub; j < cnt; j += 4 * kGroup) {
-                    uint64_t rr[4];
-#pragma unroll
-                    for (uint32_t q = 0; q < 4; ++q) rr[q] = j + q * kGroup < cnt ? src[j + q * kGroup] : 0ull;
-#pragma unroll
-                    for (uint32_t q = 0; q < 4; ++q)
-                        if (j + q * kGroup < cnt) splat_record<FOOT, S, A>(keys, rr[q], gbase);
-                }
+        for (uint32_t k = 0; k < kPer; ++k) {
+            if (cn[k] != 0u) {
+                roff[orr] = oc;
+                rloc[orr] = ((tid * kPer + k) << 16) | cs[k];
+                oc += cn[k];
+                ++orr;
             }
         }
+        if (tid == 0) roff[nruns] = total;
+        __syncthreads();
+        if (total == 0) continue;
+        const uint32_t r0 = static_cast<uint32_t>(static_cast<uint64_t>(total) * wave / 16u);
+        const uint32_t r1 = static_cast<uint32_t>(static_cast<uint64_t>(total) * (wave + 1u) / 16u);
+        if (r0 < r1)
+            splat_flat<S, 16>(v.seg + static_cast<uint64_t>(base) * P, base * P, P, keys,
+                                      roff, rloc, nruns, r0, r1, mark);
     }
     __syncthreads();
-    uint64_t* part = v.part + static_cast<uint64_t>(piece) * (A * A);
-    for (uint32_t q = tid; q < A * A; q += 1024u) part[q] = keys[q];
+    write_part<FOOT, S, A>(keys, v.part + static_cast<uint64_t>(piece) * (A * A));
     __syncthreads();
 }
 
@@ -182,8 +280,8 @@ __device__ __forceinline__ void tile_split(const TileView& v, uint32_t t, uint32
 template <int FOOT, int SHIFT>
 __global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
     using Sh = TileShape<FOOT, SHIFT>;
-    __shared__ uint64_t keys[Sh::A * Sh::A];
-    __shared__ uint32_t col[Sh::kCol];  // start << 16 | count, per bin workgroup
+    __shared__ uint64_t keys[Sh::S * Sh::S];
+    __shared__ uint32_t col[Sh::kColLds];
     uint32_t t, z;
     tile_of_block(blockIdx.x, a.v.splits, t, z);
     if (t >= a.v.ntiles) return;
@@ -284,8 +382,8 @@ __global__ __launch_bounds__(1024) void plan_kernel(TileArgs a) {
 template <int FOOT, int SHIFT>
 __global__ __launch_bounds__(1024) void tile_list_kernel(TileArgs a) {
     using Sh = TileShape<FOOT, SHIFT>;
-    __shared__ uint64_t keys[Sh::A * Sh::A];
-    __shared__ uint32_t col[Sh::kCol];
+    __shared__ uint64_t keys[Sh::S * Sh::S];
+    __shared__ uint32_t col[Sh::kColLds];
     __shared__ uint32_t next;
     const uint32_t n_items = __hip_atomic_load(&a.counters[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
@@ -305,8 +403,8 @@ __global__ __launch_bounds__(1024) void tile_list_kernel(TileArgs a) {
 template <int FOOT, int SHIFT>
 __global__ __launch_bounds__(1024) void batch_tile_kernel(BatchTileArgs a) {
     using Sh = TileShape<FOOT, SHIFT>;
-    __shared__ uint64_t keys[Sh::A * Sh::A];
-    __shared__ uint32_t col[Sh::kCol];
+    __shared__ uint64_t keys[Sh::S * Sh::S];
+    __shared__ uint32_t col[Sh::kColLds];
     const uint32_t stamp = *a.stamp_in;
     for (uint32_t it = blockIdx.x; it < a.items; it += gridDim.x) {
         const uint2 item = load_uniform(&a.item[it]);
