@@ -107,10 +107,12 @@ template <int FOOT, int SHIFT>
 struct TileShape {
     static constexpr uint32_t S = 1u << SHIFT;
     static constexpr uint32_t A = FOOT == 3 ? S + 2 : S;
-    static constexpr uint32_t kCol = 4096;  // bin workgroups per pass over the column
-    // LDS words beside the keys: run offsets (kCol + 1), run locations (kCol),
-    // one 64-word window mark per wave, and the scan's wave sums (2 x 16)
-    static constexpr uint32_t kColLds = (kCol + 1) + kCol + 16 * 64 + 32;
+    static constexpr uint32_t kCol = 4096;     // bin workgroups per pass over the column
+    static constexpr uint32_t kSeg = 1u << 18;  // records per segment of a pass
+    // LDS words beside the keys: run offsets (kCol + 1, padded to even), run
+    // address bias and index base (2 kCol), the segment's run-start bitmap
+    // (kSeg / 32) and the scan's wave sums (2 x 16)
+    static constexpr uint32_t kColLds = (kCol + 2) + 2 * kCol + kSeg / 32 + 32;
 };
 
 // Inclusive scan of two values over the 64 lanes of a wave.
@@ -125,22 +127,29 @@ __device__ __forceinline__ void wave_scan2(uint32_t& a, uint32_t& b, uint32_t la
     }
 }
 
-// Records [r0, r1) of the flat record list of one pass (the concatenation of
-// the tile's non-empty runs, run k holding records [roff[k], roff[k + 1])
-// from chunk base + (rloc[k] >> 16) at offset rloc[k] & 0xFFFF), splatted by
-// one wave. The wave takes 64 consecutive records per step, one per lane: a
-// lane finds its run from the run starts that fall inside the step's window
-// (marked in the wave's LDS mark words, gathered with a ballot, counted with
-// mbcnt), so every load of a step is contiguous and no lane waits on a
-// per-run branch. U steps are loaded before their records are splatted.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x, uint32_t lane_id) {
+    const uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(x), lane_id);
+    const uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(x >> 32), lane_id);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Records [r0, r1) of a segment starting at record s0 of the pass's flat
+// record list (the tile's non-empty runs end to end; run k holds records
+// [roff[k], roff[k + 1])), splatted by one wave; r0 - s0 is a multiple of 64.
+// The wave takes 64 consecutive records per window, one per lane. Bit p of
+// window word i of `starts` is set when a run starts at record s0 + 64 i + p,
+// so a lane's run is the window's first run plus the starts at or before it
+// (mbcnt), and the next window's first run follows by a popcount: the U
+// windows of a batch need no LDS round trip after their start words, which
+// one read brings in. runs[k] = (address bias, index base): record f of run
+// k is seg[bias + f] with point index base + local.
 template <uint32_t S, uint32_t U>
-__device__ __forceinline__ void splat_flat(const uint64_t* seg, uint32_t gbase0, uint32_t P,
-                                           uint64_t* keys, const uint32_t* roff,
-                                           const uint32_t* rloc, uint32_t nruns, uint32_t r0,
-                                           uint32_t r1, uint32_t* mark) {
+__device__ __forceinline__ void splat_segment(const uint64_t* seg, uint64_t* keys,
+                                              const uint32_t* roff, const uint2* runs,
+                                              const uint64_t* starts, uint32_t nruns,
+                                              uint32_t s0, uint32_t r0, uint32_t r1) {
     const uint32_t lane = threadIdx.x & 63u;
-    mark[lane] = 0xFFFFFFFFu;  // no window starts there
-    // run k holding record r0: roff[k] <= r0 < roff[k + 1] (roff[nruns] = total > r0)
+    // run holding record r0: roff[k] <= r0 < roff[k + 1] (roff[nruns] > r0)
     uint32_t lo = 0, hi = nruns;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -148,33 +157,29 @@ __device__ __forceinline__ void splat_flat(const uint64_t* seg, uint32_t gbase0,
         else hi = mid;
     }
     uint32_t k = lo;
+    const uint32_t wend = (r1 - s0 + 63u) >> 6;  // window words of the segment in use
     for (uint32_t w0 = r0; w0 < r1; w0 += 64u * U) {
+        const uint32_t i0 = (w0 - s0) >> 6;
+        // lane u holds the start word of window i0 + u (words past the range are 0)
+        const uint64_t mine = i0 + lane < wend && lane <= U ? starts[i0 + lane] : 0ull;
         uint64_t r[U];
         uint32_t gb[U];
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t w = w0 + 64u * u;  // window [w, w + 64)
-            // lane j holds the start of run k + 1 + j; they are increasing, the
-            // first lies past w, and at most 64 of them fall inside (w, w + 64]
-            const uint32_t b = roff[min(k + 1u + lane, nruns)];
-            const uint32_t pos = b - w;
-            if (pos < 64u) mark[pos] = w;
-            __builtin_amdgcn_wave_barrier();
-            const uint64_t starts = __ballot(mark[lane] == w);
-            const uint32_t crossed = static_cast<uint32_t>(__popcll(starts)) + (__ballot(pos == 64u) != 0);
-            // runs started at or before this lane's record
+            const uint64_t m = uniform_u64(mine, u);
+            // runs started after the window's first record, up to this lane's
+            const uint64_t after = m >> 1;
             const uint32_t upto = __builtin_amdgcn_mbcnt_hi(
-                static_cast<uint32_t>(starts >> 32),
-                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(starts), 0u)) +
-                static_cast<uint32_t>((starts >> lane) & 1ull);
-            const uint32_t f = w + lane;
-            const uint32_t kl = min(k + upto, nruns - 1u);
-            const uint32_t loc = rloc[kl], st = roff[kl];
-            const uint32_t off = (loc >> 16) * P + (loc & 0xFFFFu) + (f < r1 ? f - st : 0u);
+                static_cast<uint32_t>(after >> 32),
+                __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(after), 0u));
+            const uint32_t f = w0 + 64u * u + lane;
+            const uint2 run = runs[min(k + upto, nruns - 1u)];
+            const uint32_t off = f < r1 ? run.x + f : 0u;
             r[u] = *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(seg) +
                                                       (static_cast<uint64_t>(off) << 3));
-            gb[u] = gbase0 + (loc >> 16) * P;
-            k += crossed;
+            gb[u] = run.y;
+            const uint64_t next = uniform_u64(mine, u + 1u);
+            k += static_cast<uint32_t>(__popcll(after)) + static_cast<uint32_t>(next & 1ull);
         }
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u)
@@ -188,29 +193,30 @@ __device__ __forceinline__ void splat_flat(const uint64_t* seg, uint32_t gbase0,
 // synchronised.
 //
 // Per pass over up to kCol bin workgroups: each thread reads the (start,
-// end) pairs of 4 consecutive workgroups from the table, a block scan over
-// the non-empty runs gives their flat offsets (roff) and compacted locations
-// (rloc), and the flat record list is cut into 16 equal ranges, one per wave.
-// A wave's work thus depends on the records, not on how they fall into runs.
+// end) pairs of 4 consecutive workgroups from the table, and a block scan
+// over the non-empty runs gives their flat offsets (roff) and locations. The
+// flat record list is then taken in segments of up to kSeg records: the run
+// starts of a segment are marked in an LDS bitmap, and its 64-record windows
+// are cut into 16 equal ranges, one per wave. A wave's work thus depends on
+// the records, not on how they fall into runs.
 template <int FOOT, int SHIFT>
 __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32_t w_lo,
                                            uint32_t w_hi, uint32_t piece, uint32_t P,
                                            uint64_t* keys, uint32_t* lds) {
     using Sh = TileShape<FOOT, SHIFT>;
-    constexpr uint32_t S = Sh::S, A = Sh::A, kCol = Sh::kCol;
+    constexpr uint32_t S = Sh::S, A = Sh::A, kCol = Sh::kCol, kSeg = Sh::kSeg;
     constexpr uint32_t kPer = kCol / 1024u;  // bin workgroups per thread and pass
     uint32_t* roff = lds;
-    uint32_t* rloc = roff + kCol + 1;
-    uint32_t* marks = rloc + kCol;
-    uint32_t* wsum = marks + 16 * 64;  // [0, 16): counts, [16, 32): runs
+    uint2* runs = reinterpret_cast<uint2*>(lds + kCol + 2);
+    uint32_t* bits = lds + kCol + 2 + 2 * kCol;
+    uint32_t* wsum = bits + kSeg / 32;  // [0, 16): records, [16, 32): runs
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    uint32_t* mark = marks + wave * 64u;
     for (uint32_t q = tid; q < S * S; q += 1024u) keys[q] = kEmptyKey;
     const uint32_t stride = v.ntiles + 1u;
 
     for (uint32_t base = w_lo; base < w_hi; base += kCol) {
         const uint32_t nb = min(kCol, w_hi - base);
-        __syncthreads();  // keys initialised / previous pass done with roff, rloc
+        __syncthreads();  // keys initialised / previous pass done with the LDS
         // Branch-free: lanes past the column's end read its last row (count
         // forced to 0), so all of a lane's table loads are in flight together.
         uint32_t cs[kPer], cn[kPer];
@@ -247,20 +253,34 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
 #pragma unroll
         for (uint32_t k = 0; k < kPer; ++k) {
             if (cn[k] != 0u) {
+                const uint32_t c = tid * kPer + k;
                 roff[orr] = oc;
-                rloc[orr] = ((tid * kPer + k) << 16) | cs[k];
+                // record f of this run is seg[base P + c P + start + f - oc]
+                runs[orr] = make_uint2(c * P + cs[k] - oc, (base + c) * P);
                 oc += cn[k];
                 ++orr;
             }
         }
         if (tid == 0) roff[nruns] = total;
-        __syncthreads();
-        if (total == 0) continue;
-        const uint32_t r0 = static_cast<uint32_t>(static_cast<uint64_t>(total) * wave / 16u);
-        const uint32_t r1 = static_cast<uint32_t>(static_cast<uint64_t>(total) * (wave + 1u) / 16u);
-        if (r0 < r1)
-            splat_flat<S, 16>(v.seg + static_cast<uint64_t>(base) * P, base * P, P, keys,
-                                      roff, rloc, nruns, r0, r1, mark);
+        const uint64_t* seg = v.seg + static_cast<uint64_t>(base) * P;
+        for (uint32_t s0 = 0; s0 < total; s0 += kSeg) {
+            const uint32_t len = min(kSeg, total - s0);
+            const uint32_t words = ((len + 63u) >> 6) * 2u;
+            __syncthreads();  // runs written / previous segment done with the bitmap
+            for (uint32_t q = tid; q < words; q += 1024u) bits[q] = 0u;
+            __syncthreads();
+            for (uint32_t k = tid; k < nruns; k += 1024u) {
+                const uint32_t pos = roff[k] - s0;
+                if (pos < len) atomicOr(&bits[pos >> 5], 1u << (pos & 31u));
+            }
+            __syncthreads();
+            const uint32_t nwin = (len + 63u) >> 6;
+            const uint32_t r0 = s0 + (nwin * wave / 16u) * 64u;
+            const uint32_t r1 = s0 + min(len, (nwin * (wave + 1u) / 16u) * 64u);
+            if (r0 < r1)
+                splat_segment<S, 12>(seg, keys, roff, runs,
+                                     reinterpret_cast<const uint64_t*>(bits), nruns, s0, r0, r1);
+        }
     }
     __syncthreads();
     write_part<FOOT, S, A>(keys, v.part + static_cast<uint64_t>(piece) * (A * A));
