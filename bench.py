@@ -32,8 +32,12 @@ CSRC = os.path.join(ROOT, "paper_2504_20937_amd", "csrc")
 # this benchmark's default workload (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch), scaled by what the same counters read for a plain 256 MiB device
 # copy (FETCH_SIZE reads half the copied bytes: x2; WRITE_SIZE reads them
-# all: x1). Keyed by a digest of the kernel sources: any change to them makes
-# the entry stale and the reported traffic null until it is measured again.
+# all: x1). Keyed by a digest of the sources the kernel is built from: any
+# change to them makes the entry stale and the reported traffic null until it
+# is measured again.
+KERNEL_SOURCES = {
+    "bin_kernel": ["mm_bin_plain.hip", "mm_bin_dev.h", "mm_device.h", "mm_internal.h"],
+}
 TRAFFIC = {
     "bin_kernel": {"digest": "1be659fb7853545d", "fetch_kib": 98450.0, "write_kib": 344200.0,
                    "fetch_scale": 2.0, "write_scale": 1.0},
@@ -42,20 +46,19 @@ POINT_BYTES = 24   # float3 read + write per point and frame
 PIXEL_BYTES = 20   # key read + empty-key write (8 + 8) and RGBA8 write (4)
 
 
-def kernel_digest() -> str:
+def kernel_digest(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".h")):
-            h.update(f.encode())
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(fh.read())
+    for f in sorted(KERNEL_SOURCES[kernel]):
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
     e = TRAFFIC.get(kernel)
-    if not e or e["digest"] != kernel_digest():
+    if not e or e["digest"] != kernel_digest(kernel):
         return None
     return (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"]) * 1024.0
 
@@ -448,6 +451,8 @@ def main() -> int:
     ap.add_argument("--piece-records", type=int, default=0,
                     help="frame: records per balanced tile piece (0 auto or -1: static splits)")
     ap.add_argument("--autotune", action="store_true", help="time the shapes, keep the fastest")
+    ap.add_argument("--overlap", action="store_true",
+                    help="frame: bin frame f while frame f - 1 is drawn (mm_set_frame_overlap)")
     ap.add_argument("--hostcopy-frames", type=int, default=10, help="hostcopy: frames timed")
     ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy"],
                     default="frame",
@@ -517,6 +522,8 @@ def main() -> int:
         mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits, args.bin_threads, pieces)
     tuning = mm.mm_get_tuning(view)
     mode = "direct" if tuning[0] == mm.MM_SPLAT_DIRECT else "binned"
+    if args.overlap:
+        mm.mm_set_frame_overlap(view, True)
     print(f"bench: {n} points, {w}x{h}, warmup {W}, timed {K}, splat {mode} {tuning}",
           file=sys.stderr, flush=True)
     for f in range(W):
@@ -529,6 +536,7 @@ def main() -> int:
         f = W + k
         mm.mm_set_camera(view, cams[f])
         mm.mm_step_render(view, f)
+    mm.mm_flush_frame(view)  # with overlap, the last frame is drawn inside the timed region
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     splat_ms, resolve_ms, frame_ms = mm.mm_profile_end(view, K)
@@ -557,7 +565,9 @@ def main() -> int:
         "config": {"workload": f"3d-{args.dist}-2^{args.log2n}pts-{w}x{h}-orbit-1deg"
                                + (f"-{args.footprint}x{args.footprint}" if args.footprint != 1 else ""),
                    "points": n, "width": w, "height": h, "footprint": args.footprint,
-                   "amplitude": 0.001, "graph": "one hipGraph per frame",
+                   "amplitude": 0.001,
+                   "graph": ("bin of frame f beside the draw of frame f - 1 (two streams)"
+                             if args.overlap else "one hipGraph per frame"),
                    "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2],
                    "splits": tuning[3], "bin_threads": tuning[4], "piece_records": tuning[5]},
         "frames_per_s": K / elapsed,

@@ -138,13 +138,37 @@ mm_status mm_render(mm_view view);
  * launch on the stream. Equivalent to mm_step then mm_render. */
 mm_status mm_step_render(mm_view view, uint32_t step);
 
+/* Frame overlap, the device form of the paper's ping-pong scheme (section
+ * "Synchronization": one buffer is displayed while the other is written)
+ * with the two sides unsynchronised (the study of section "Performance
+ * Benchmark" with synchronization disabled). With on = 1 (binned splat only), frame f is
+ * displaced, projected and binned into one of two record sets on the
+ * instance stream while frame f - 1 is drawn from the other set on a render
+ * stream of the view's own, so the two passes of consecutive frames run
+ * side by side. mm_step_render then leaves the frame buffer one frame
+ * behind: after the call for step f it holds (or will hold) frame f - 1, and
+ * frames are still bit-identical to the serial path's. Every tile not drawn
+ * in a frame is cleared. on = 0 returns to the serial frame graph.
+ * Reallocates the view's scratch (a second set of records, table and tile
+ * stamps) and synchronises. MM_ERR_UNSUPPORTED when the view's splat is not
+ * binned; mm_set_tuning to a direct splat is then refused while it is on. */
+mm_status mm_set_frame_overlap(mm_view view, uint32_t on);
+
+/* Overlapped views: draws the frame of the last mm_step_render (the pending
+ * frame) and makes the instance stream wait for it, so the frame buffer
+ * holds the last frame for work after it in stream order. Does not
+ * synchronise the host. A no-op for views without overlap. */
+mm_status mm_flush_frame(mm_view view);
+
 /* *dev_rgba receives the device address of the view's frame (width *
  * height uint32). It stays valid until the view is destroyed; its content
- * is that of the last frame in stream order. */
+ * is that of the last frame in stream order (with frame overlap, of the
+ * last frame drawn: call mm_flush_frame before reading it on the stream). */
 mm_status mm_frame_device_ptr(mm_view view, const uint32_t** dev_rgba);
 
 /* Copies the frame to host memory (bytes >= width * height * 4) after all
- * enqueued work. Synchronises. */
+ * enqueued work (with frame overlap: the last frame drawn; the pending frame
+ * is drawn by mm_flush_frame or the next mm_step_render). Synchronises. */
 mm_status mm_read_frame(mm_view view, void* host_rgba, size_t bytes);
 
 /* Splat strategy of a view (all give the same frames, bit for bit).

@@ -147,6 +147,8 @@ def _declare(L):
         "mm_step": ([_vp, C.c_uint32], _status),
         "mm_render": ([_vp], _status),
         "mm_step_render": ([_vp, C.c_uint32], _status),
+        "mm_set_frame_overlap": ([_vp, C.c_uint32], _status),
+        "mm_flush_frame": ([_vp], _status),
         "mm_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
         "mm_read_frame": ([_vp, _vp, C.c_size_t], _status),
         "mm_set_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
@@ -323,6 +325,16 @@ def mm_render(view: int) -> None:
 
 def mm_step_render(view: int, step: int) -> None:
     _check(lib().mm_step_render(view, step), "mm_step_render")
+
+
+def mm_set_frame_overlap(view: int, on: bool) -> None:
+    """Frame overlap: frame f is binned while frame f - 1 is drawn; the frame
+    buffer then lags mm_step_render by one frame until mm_flush_frame."""
+    _check(lib().mm_set_frame_overlap(view, int(on)), "mm_set_frame_overlap")
+
+
+def mm_flush_frame(view: int) -> None:
+    _check(lib().mm_flush_frame(view), "mm_flush_frame")
 
 
 def mm_frame_device_ptr(view: int) -> int:

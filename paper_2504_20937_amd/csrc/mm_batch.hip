@@ -673,7 +673,8 @@ mm_status mm_batch_profile_begin(mm_batch b, uint32_t capacity) {
     MM_HIP(hipStreamSynchronize(b->inst->stream));
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     b->events.assign(2ull * capacity, nullptr);
-    for (auto& e : b->events) MM_HIP(hipEventCreate(&e));
+    // timing only: no system-scope fence per event
+    for (auto& e : b->events) MM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     b->prof_cap = capacity;
     b->prof_count = 0;
     b->profiling = true;

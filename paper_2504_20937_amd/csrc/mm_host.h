@@ -165,8 +165,9 @@ std::string device_arch(int device);
 template <typename F>
 float time_frames(hipStream_t s, uint32_t frames, F fn) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess) return -1.0f;
-    if (hipEventCreate(&b) != hipSuccess) {
+    // timing only: no system-scope fence per event
+    if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return -1.0f;
+    if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
         (void)hipEventDestroy(a);
         return -1.0f;
     }

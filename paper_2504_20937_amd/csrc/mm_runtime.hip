@@ -63,6 +63,20 @@ struct mm_view_s {
     std::vector<hipEvent_t> events;  // 3 per profiled frame
     uint32_t prof_cap = 0, prof_count = 0;
     bool profiling = false;
+    // Frame overlap (binned only): frame f is binned into record set f & 1 on
+    // the instance stream while frame f - 1 is drawn from the other set on
+    // the render stream. Set 1 mirrors seg / table / active.
+    bool overlap = false;
+    uint64_t* seg1 = nullptr;
+    uint16_t* table1 = nullptr;
+    uint32_t* active1 = nullptr;
+    mm::BinArgs bargs1{};
+    mm::TileArgs targs1{};
+    hipStream_t rstream = nullptr;
+    hipEvent_t ev_bin[2] = {nullptr, nullptr};     // set binned (instance stream)
+    hipEvent_t ev_drawn[2] = {nullptr, nullptr};   // set drawn (render stream)
+    int pending = -1;                              // set binned, not yet drawn
+    int last_drawn = -1;                           // set whose frame the colour holds
 };
 
 namespace {
@@ -134,6 +148,12 @@ void free_splat_buffers(mm_view v) {
                     static_cast<void*>(v->piece_first), static_cast<void*>(v->items),
                     static_cast<void*>(v->counters)})
         if (p) (void)hipFree(p);
+    for (void* p : {static_cast<void*>(v->seg1), static_cast<void*>(v->table1),
+                    static_cast<void*>(v->active1)})
+        if (p) (void)hipFree(p);
+    v->seg1 = nullptr;
+    v->table1 = nullptr;
+    v->active1 = nullptr;
     v->tile_total = nullptr;
     v->piece_first = nullptr;
     v->items = nullptr;
@@ -292,6 +312,29 @@ mm_status setup_splat(mm_view v) {
         t.items = v->items;
         t.counters = v->counters;
         t.piece_records = balanced ? v->tuning.piece_records : 0u;
+        if (v->overlap) {
+            // second record set; every tile not drawn in a frame is cleared,
+            // since the other set's stamps say nothing about this frame buffer
+            e = alloc_n(&v->seg1, static_cast<uint64_t>(v->num_wg) * P);
+            if (e == hipSuccess) e = alloc_n(&v->table1, static_cast<uint64_t>(v->num_wg) * (v->ntiles + 1));
+            if (e == hipSuccess) e = alloc_n(&v->active1, static_cast<uint64_t>(v->ntiles) + 1);
+            if (e == hipSuccess)
+                e = hipMemsetAsync(v->active1, 0, (static_cast<size_t>(v->ntiles) + 1) * 4, inst->stream);
+            if (e != hipSuccess) return hip_fail(e, "overlapped record set");
+            t.v.full_clear = 1;
+            v->bargs1 = b;
+            v->bargs1.v.seg = v->seg1;
+            v->bargs1.v.table = v->table1;
+            v->bargs1.v.active = v->active1;
+            v->bargs1.stamp_out = v->active1 + v->ntiles;
+            v->targs1 = t;
+            v->targs1.v.seg = v->seg1;
+            v->targs1.v.table = v->table1;
+            v->targs1.v.active = v->active1;
+            v->targs1.stamp_in = v->active1 + v->ntiles;
+        }
+        v->pending = -1;
+        v->last_drawn = -1;
         v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, nthreads, v->args.c.n, v->ntiles));
         if (balanced) {
             int cus = 0;
@@ -311,7 +354,10 @@ mm_status setup_splat(mm_view v) {
     return build_graph(v, false, v->plain);
 }
 
+void destroy_overlap(mm_view v);
+
 void teardown_splat(mm_view v) {
+    if (v->rstream) (void)hipStreamSynchronize(v->rstream);
     destroy_graph(v->plain);
     destroy_graph(v->timed);
     v->profiling = false;
@@ -320,6 +366,7 @@ void teardown_splat(mm_view v) {
 
 void destroy_view_resources(mm_view v) {
     teardown_splat(v);
+    destroy_overlap(v);
     for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
     v->events.clear();
     if (v->colour) (void)hipFree(v->colour);
@@ -338,15 +385,93 @@ mm_status validate_desc(mm_instance inst, const mm_view_desc* d) {
     return MM_OK;
 }
 
-// Next frame stamp of a binned view; on wrap-around the tile stamps restart.
+mm_status flush_frame(mm_view v);
+
+// Next frame stamp of a binned view; on wrap-around the tile stamps restart
+// (an overlapped view first draws its pending frame and lets the render
+// stream drain, since the stamps of both record sets are reset).
 mm_status next_stamp(mm_view v) {
     if (++v->stamp == 0) {
+        if (v->overlap) {
+            MM_TRY(flush_frame(v));
+            MM_HIP(hipStreamSynchronize(v->rstream));
+            MM_HIP(hipMemsetAsync(v->active1, 0, (static_cast<size_t>(v->ntiles) + 1) * 4,
+                                  v->inst->stream));
+        }
         MM_HIP(hipMemsetAsync(v->active, 0, (static_cast<size_t>(v->ntiles) + 1) * 4,
                               v->inst->stream));
         v->stamp = 1;
     }
     v->bargs.stamp = v->stamp;
+    v->bargs1.stamp = v->stamp;
     return MM_OK;
+}
+
+mm::BinArgs& set_bin(mm_view v, int k) { return k ? v->bargs1 : v->bargs; }
+mm::TileArgs& set_tile(mm_view v, int k) { return k ? v->targs1 : v->targs; }
+
+// Draws record set k (binned on the instance stream) on the render stream:
+// the tile, merge (and seam) kernels of the frame, then marks the set free.
+mm_status draw_set(mm_view v, int k) {
+    MM_HIP(hipStreamWaitEvent(v->rstream, v->ev_bin[k], 0));
+    void* args[] = {&set_tile(v, k)};
+    for (size_t n = 1; n < v->nodes.size(); ++n)
+        MM_HIP(hipLaunchKernel(v->nodes[n].func, v->nodes[n].grid, v->nodes[n].block, args,
+                               v->nodes[n].shared, v->rstream));
+    MM_HIP(hipEventRecord(v->ev_drawn[k], v->rstream));
+    v->last_drawn = k;
+    return MM_OK;
+}
+
+// Draws the pending frame of an overlapped view, and makes the instance
+// stream wait for the last draw, so work after it in stream order sees the
+// frame buffer of the last frame.
+mm_status flush_frame(mm_view v) {
+    if (!v->overlap) return MM_OK;
+    if (v->pending >= 0) {
+        MM_TRY(draw_set(v, v->pending));
+        v->pending = -1;
+    }
+    if (v->last_drawn >= 0) MM_HIP(hipStreamWaitEvent(v->inst->stream, v->ev_drawn[v->last_drawn], 0));
+    return MM_OK;
+}
+
+// One overlapped frame: bin (with displacement when phase says so) into the
+// free record set on the instance stream, and draw the pending set on the
+// render stream beside it. With profiling on, events go before and after the
+// bin kernel (instance stream) and after the draw (render stream).
+mm_status overlap_frame(mm_view v, mm::Phase phase, uint32_t step) {
+    MM_TRY(next_stamp(v));
+    const int k = static_cast<int>(v->stamp & 1u);
+    mm::BinArgs& b = set_bin(v, k);
+    b.c.step = step;
+    hipStream_t s = v->inst->stream;
+    // the last draw of set k has read its records
+    MM_HIP(hipStreamWaitEvent(s, v->ev_drawn[k], 0));
+    hipEvent_t* ev = nullptr;
+    if (v->profiling && v->prof_count < v->prof_cap) ev = &v->events[3ull * v->prof_count++];
+    if (ev) MM_HIP(hipEventRecord(ev[0], s));
+    const mm::Launch bl = mm::bin_launch(static_cast<int>(v->desc.domain), v->desc.wrap != 0, phase,
+                                         static_cast<int>(v->tuning.points_per_thread),
+                                         v->tuning.bin_threads, v->args.c.n, v->ntiles);
+    void* args[] = {&b};
+    MM_HIP(hipLaunchKernel(bl.func, bl.grid, bl.block, args, bl.shared, s));
+    if (ev) MM_HIP(hipEventRecord(ev[1], s));
+    MM_HIP(hipEventRecord(v->ev_bin[k], s));
+    if (v->pending >= 0) MM_TRY(draw_set(v, v->pending));
+    if (ev) MM_HIP(hipEventRecord(ev[2], v->pending >= 0 ? v->rstream : s));
+    v->pending = k;
+    return MM_OK;
+}
+
+void destroy_overlap(mm_view v) {
+    for (hipEvent_t* e : {&v->ev_bin[0], &v->ev_bin[1], &v->ev_drawn[0], &v->ev_drawn[1]}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
+    }
+    if (v->rstream) (void)hipStreamDestroy(v->rstream);
+    v->rstream = nullptr;
+    v->overlap = false;
 }
 
 }  // namespace
@@ -587,7 +712,10 @@ mm_status mm_set_tuning(mm_view v, const mm_tuning* req) {
     if (!v || !req) return fail(MM_ERR_INVALID_ARG, "set_tuning: null argument");
     mm_tuning t{};
     MM_TRY(resolve_tuning(v->desc, *req, t));
+    if (v->overlap && t.splat != MM_SPLAT_BINNED)
+        return fail(MM_ERR_UNSUPPORTED, "set_tuning: frame overlap needs the binned splat");
     DeviceGuard guard(v->inst->device);
+    MM_TRY(flush_frame(v));
     MM_HIP(hipStreamSynchronize(v->inst->stream));
     teardown_splat(v);
     v->tuning = t;
@@ -615,7 +743,8 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     void* saved = nullptr;
     MM_HIP(hipMalloc(&saved, bytes));
     hipError_t e = hipMemcpyAsync(saved, v->position->ptr, bytes, hipMemcpyDeviceToDevice, inst->stream);
-    std::vector<mm_tuning> cands = {{MM_SPLAT_DIRECT, 0, 0, 0, 0, 0}};
+    std::vector<mm_tuning> cands;
+    if (!v->overlap) cands.push_back({MM_SPLAT_DIRECT, 0, 0, 0, 0, 0});
     for (uint32_t tile : {32u, 64u})
         for (uint32_t threads : {256u, 1024u})
             for (uint32_t ppt : {8u, 16u}) {
@@ -630,7 +759,13 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
         if (e != hipSuccess) break;
         mm_tuning r{};
         if (resolve_tuning(d, c, r) != MM_OK || mm_set_tuning(v, &c) != MM_OK) continue;
-        const float ms = time_frames(inst->stream, frames, [&] { return mm_step_render(v, 0); });
+        // an overlapped view draws its last frame inside the timed region
+        uint32_t calls = 0;
+        const float ms = time_frames(inst->stream, frames, [&] {
+            mm_status st = mm_step_render(v, 0);
+            if (st == MM_OK && ++calls == frames + 1) st = flush_frame(v);
+            return st;
+        });
         if (ms > 0.0f && (best_ms == 0.0f || ms < best_ms)) {
             best_ms = ms;
             best = r;
@@ -663,6 +798,7 @@ mm_status mm_set_camera(mm_view v, const float m[16]) {
     std::memcpy(v->desc.view_proj, m, sizeof(float) * 16);
     set_camera_rows(v->args.g, m);
     set_camera_rows(v->bargs.v.g, m);
+    set_camera_rows(v->bargs1.v.g, m);
     return MM_OK;
 }
 
@@ -692,6 +828,10 @@ mm_status mm_render(mm_view v) {
         MM_HIP(mm::launch_resolve(v->rargs, s));
         return MM_OK;
     }
+    if (v->overlap) {
+        MM_TRY(overlap_frame(v, mm::kRender, 0));
+        return flush_frame(v);
+    }
     MM_TRY(next_stamp(v));
     const mm::Launch b = mm::bin_launch(dim, v->desc.wrap != 0, mm::kRender,
                                         static_cast<int>(v->tuning.points_per_thread),
@@ -709,6 +849,7 @@ mm_status mm_render(mm_view v) {
 mm_status mm_step_render(mm_view v, uint32_t step) {
     MM_TRY(require_ready(v, "step_render"));
     DeviceGuard guard(v->inst->device);
+    if (v->overlap) return overlap_frame(v, mm::kDisplaceRender, step);
     void* first_arg;
     if (binned(v)) {
         MM_TRY(next_stamp(v));
@@ -734,6 +875,40 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
     return MM_OK;
 }
 
+mm_status mm_set_frame_overlap(mm_view v, uint32_t on) {
+    if (!v) return fail(MM_ERR_INVALID_ARG, "set_frame_overlap: null view");
+    if (on > 1) return fail(MM_ERR_INVALID_ARG, "set_frame_overlap: on must be 0 or 1");
+    if ((on != 0) == v->overlap) return MM_OK;
+    if (on && !binned(v)) return fail(MM_ERR_UNSUPPORTED, "set_frame_overlap: the view's splat is not binned");
+    if (on && !v->plain.exec) return fail(MM_ERR_INVALID_ARG, "set_frame_overlap: view has no usable tuning");
+    DeviceGuard guard(v->inst->device);
+    MM_TRY(flush_frame(v));
+    MM_HIP(hipStreamSynchronize(v->inst->stream));
+    teardown_splat(v);
+    destroy_overlap(v);
+    if (on) {
+        hipError_t e = hipStreamCreateWithFlags(&v->rstream, hipStreamNonBlocking);
+        for (hipEvent_t* ev : {&v->ev_bin[0], &v->ev_bin[1], &v->ev_drawn[0], &v->ev_drawn[1]})
+            // ordering between two streams of one device: a device-scope release
+            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventReleaseToDevice);
+        if (e != hipSuccess) {
+            destroy_overlap(v);
+            (void)setup_splat(v);
+            return hip_fail(e, "set_frame_overlap: render stream");
+        }
+        v->overlap = true;
+    }
+    const mm_status st = setup_splat(v);
+    if (st != MM_OK) teardown_splat(v);
+    return st;
+}
+
+mm_status mm_flush_frame(mm_view v) {
+    if (!v) return fail(MM_ERR_INVALID_ARG, "flush_frame: null view");
+    DeviceGuard guard(v->inst->device);
+    return flush_frame(v);
+}
+
 mm_status mm_frame_device_ptr(mm_view v, const uint32_t** dev_rgba) {
     if (!v || !dev_rgba) return fail(MM_ERR_INVALID_ARG, "frame_device_ptr: null argument");
     *dev_rgba = v->colour;
@@ -745,6 +920,8 @@ mm_status mm_read_frame(mm_view v, void* host_rgba, size_t bytes) {
     const size_t need = static_cast<size_t>(v->desc.width) * v->desc.height * sizeof(uint32_t);
     if (bytes < need) return fail(MM_ERR_INVALID_ARG, "read_frame: %zu bytes < %zu", bytes, need);
     DeviceGuard guard(v->inst->device);
+    if (v->overlap && v->last_drawn >= 0)
+        MM_HIP(hipStreamWaitEvent(v->inst->stream, v->ev_drawn[v->last_drawn], 0));
     MM_HIP(hipMemcpyAsync(host_rgba, v->colour, need, hipMemcpyDeviceToHost, v->inst->stream));
     MM_HIP(hipStreamSynchronize(v->inst->stream));
     return MM_OK;
@@ -759,7 +936,9 @@ mm_status mm_profile_begin(mm_view v, uint32_t capacity) {
     destroy_graph(v->timed);
     for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
     v->events.assign(3ull * capacity, nullptr);
-    for (auto& e : v->events) MM_HIP(hipEventCreate(&e));
+    // timing only: no system-scope fence (a cache writeback and invalidate
+    // per event would slow the frame being measured)
+    for (auto& e : v->events) MM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     MM_TRY(build_graph(v, true, v->timed));
     v->prof_cap = capacity;
     v->prof_count = 0;
@@ -773,6 +952,7 @@ mm_status mm_profile_end(mm_view v, float* splat_ms, float* resolve_ms, float* f
     if (!v->profiling) return fail(MM_ERR_INVALID_ARG, "profile_end: no profile_begin");
     DeviceGuard guard(v->inst->device);
     MM_HIP(hipStreamSynchronize(v->inst->stream));
+    if (v->rstream) MM_HIP(hipStreamSynchronize(v->rstream));
     for (uint32_t k = 0; k < v->prof_count; ++k) {
         float t = 0.0f;
         hipEvent_t* e = &v->events[3ull * k];

@@ -153,3 +153,19 @@ def test_server_struct_layouts_match_the_header(tmp_path):
         exprs.append(f"sizeof({cname})")
         expect.append(C.sizeof(py))
     assert _c_layout(tmp_path, exprs) == expect
+
+
+def test_build_rejects_kernels_with_scratch():
+    """The build reads hipcc's resource-usage remarks and refuses a kernel that
+    spills registers to scratch (the kernels are written to need none)."""
+    from paper_2504_20937_amd import build
+    remarks = "\n".join([
+        "a.hip:1:1: remark: Function Name: good_kernel [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     VGPRs: 64 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:1:1: remark:     ScratchSize [bytes/lane]: 0 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark: Function Name: bad_kernel [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     VGPRs: 128 [-Rpass-analysis=kernel-resource-usage]",
+        "a.hip:9:1: remark:     ScratchSize [bytes/lane]: 12 [-Rpass-analysis=kernel-resource-usage]",
+    ])
+    assert build._spilling_kernels(remarks) == ["bad_kernel (12 B/lane)"]
+    assert build._spilling_kernels(remarks.split("\na.hip:9")[0]) == []
