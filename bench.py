@@ -39,7 +39,7 @@ KERNEL_SOURCES = {
     "bin_kernel": ["mm_bin_plain.hip", "mm_bin_dev.h", "mm_device.h", "mm_internal.h"],
 }
 TRAFFIC = {
-    "bin_kernel": {"digest": "1be659fb7853545d", "fetch_kib": 98450.0, "write_kib": 344200.0,
+    "bin_kernel": {"digest": "e71821ef203dbede", "fetch_kib": 98394.4, "write_kib": 335986.5,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 POINT_BYTES = 24   # float3 read + write per point and frame

@@ -197,8 +197,9 @@ typedef struct {
     uint32_t piece_records;     /* binned: 1024 .. 2^20 balances the depth test by
                                    load: every tile is cut into pieces of about this
                                    many records (at least points / 65535), taken by a
-                                   persistent grid; MM_PIECES_STATIC or 0 (auto):
-                                   `splits` workgroups per tile */
+                                   persistent grid; MM_PIECES_STATIC: `splits`
+                                   workgroups per tile; 0 = auto (static below
+                                   8192 bin workgroups, else balanced by load) */
 } mm_tuning;
 
 #define MM_PIECES_STATIC 0xFFFFFFFFu

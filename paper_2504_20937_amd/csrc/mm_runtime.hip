@@ -189,9 +189,20 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
     if (out.tile == 0) out.tile = tiles(32) <= 4096u ? 32u : 64u;
     if (out.points_per_thread == 0) out.points_per_thread = 8;
     if (out.bin_threads == 0) out.bin_threads = 1024;
-    // Auto is static splits: on the 1080p and 4K workloads the balanced
-    // pass's count and plan kernels cost more than the imbalance they remove.
-    if (out.piece_records == 0) out.piece_records = MM_PIECES_STATIC;
+    // Auto: static splits up to 8191 bin workgroups (2^26 points at the
+    // default chunk), where the balanced pass's count and plan kernels cost
+    // more than the imbalance they remove; beyond, balanced pieces of about
+    // N / 1024 records (2^28 clustered points at 4K: 1.5x the static pass).
+    if (out.piece_records == 0) {
+        const uint64_t P = static_cast<uint64_t>(out.bin_threads) * out.points_per_thread;
+        const uint64_t wgs = (d.element_count + P - 1) / P;
+        if (wgs < 8192) {
+            out.piece_records = MM_PIECES_STATIC;
+        } else {
+            const uint64_t r = (d.element_count / 1024 + 1023) / 1024 * 1024;
+            out.piece_records = static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(r, 4096), 1u << 20));
+        }
+    }
     if (out.piece_records != MM_PIECES_STATIC) {
         // balanced by load; a tile's piece count must fit 16 bits
         if (out.piece_records < 1024 || out.piece_records > (1u << 20))

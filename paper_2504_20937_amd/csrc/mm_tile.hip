@@ -68,6 +68,12 @@ __device__ __forceinline__ uint32_t tile_flag(const TileView& v, uint32_t t) {
 // minima (exact: a pixel's key is the minimum over the records centred in
 // its neighbourhood, in any grouping), so every record costs one LDS atomic
 // whatever the footprint.
+// Threads of a tile workgroup (the depth test of one tile or one piece of
+// it). 512 keeps two or three workgroups resident per CU, so one
+// workgroup's table reads and scans overlap another's record stream.
+constexpr uint32_t kTileThreads = 512;
+constexpr uint32_t kTileWaves = kTileThreads / 64;
+
 template <uint32_t S>
 __device__ __forceinline__ void splat_record(uint64_t* keys, uint64_t r, uint32_t gbase) {
     const uint32_t lo = static_cast<uint32_t>(r);
@@ -83,9 +89,9 @@ template <int FOOT, uint32_t S, uint32_t A>
 __device__ __forceinline__ void write_part(const uint64_t* keys, uint64_t* part) {
     const uint32_t tid = threadIdx.x;
     if constexpr (FOOT == 1) {
-        for (uint32_t q = tid; q < S * S; q += 1024u) part[q] = keys[q];
+        for (uint32_t q = tid; q < S * S; q += kTileThreads) part[q] = keys[q];
     } else {
-        for (uint32_t q = tid; q < A * A; q += 1024u) {
+        for (uint32_t q = tid; q < A * A; q += kTileThreads) {
             const uint32_t i = q / A, j = q % A;
             uint64_t m = kEmptyKey;
 #pragma unroll
@@ -107,12 +113,12 @@ template <int FOOT, int SHIFT>
 struct TileShape {
     static constexpr uint32_t S = 1u << SHIFT;
     static constexpr uint32_t A = FOOT == 3 ? S + 2 : S;
-    static constexpr uint32_t kCol = 4096;     // bin workgroups per pass over the column
-    static constexpr uint32_t kSeg = 1u << 18;  // records per segment of a pass
+    static constexpr uint32_t kCol = 2048;     // bin workgroups per pass over the column
+    static constexpr uint32_t kSeg = 1u << 17;  // records per segment of a pass
     // LDS words beside the keys: run offsets (kCol + 1, padded to even), run
     // address bias and index base (2 kCol), the segment's run-start bitmap
-    // (kSeg / 32) and the scan's wave sums (2 x 16)
-    static constexpr uint32_t kColLds = (kCol + 2) + 2 * kCol + kSeg / 32 + 32;
+    // (kSeg / 32) and the scan's wave sums (2 per wave)
+    static constexpr uint32_t kColLds = (kCol + 2) + 2 * kCol + kSeg / 32 + 2 * kTileWaves;
 };
 
 // Inclusive scan of two values over the 64 lanes of a wave.
@@ -188,7 +194,7 @@ __device__ __forceinline__ void splat_segment(const uint64_t* seg, uint64_t* key
 }
 
 // Tile t over bin workgroups [w_lo, w_hi): the per-pixel minimum of their
-// records, written as partial key block `piece` of v.part. 1024 threads; keys
+// records, written as partial key block `piece` of v.part. kTileThreads threads; keys
 // (S * S centre minima) and lds (kColLds words) are LDS. Ends with the block
 // synchronised.
 //
@@ -205,13 +211,13 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
                                            uint64_t* keys, uint32_t* lds) {
     using Sh = TileShape<FOOT, SHIFT>;
     constexpr uint32_t S = Sh::S, A = Sh::A, kCol = Sh::kCol, kSeg = Sh::kSeg;
-    constexpr uint32_t kPer = kCol / 1024u;  // bin workgroups per thread and pass
+    constexpr uint32_t kPer = kCol / kTileThreads;  // bin workgroups per thread and pass
     uint32_t* roff = lds;
     uint2* runs = reinterpret_cast<uint2*>(lds + kCol + 2);
     uint32_t* bits = lds + kCol + 2 + 2 * kCol;
-    uint32_t* wsum = bits + kSeg / 32;  // [0, 16): records, [16, 32): runs
+    uint32_t* wsum = bits + kSeg / 32;  // [0, waves): records, [waves, 2 waves): runs
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    for (uint32_t q = tid; q < S * S; q += 1024u) keys[q] = kEmptyKey;
+    for (uint32_t q = tid; q < S * S; q += kTileThreads) keys[q] = kEmptyKey;
     const uint32_t stride = v.ntiles + 1u;
 
     for (uint32_t base = w_lo; base < w_hi; base += kCol) {
@@ -238,13 +244,13 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
         wave_scan2(ic, ir, lane);
         if (lane == 63u) {
             wsum[wave] = ic;
-            wsum[16 + wave] = ir;
+            wsum[kTileWaves + wave] = ir;
         }
         __syncthreads();
         uint32_t total = 0, nruns = 0, oc = ic - tc, orr = ir - tr;
 #pragma unroll
-        for (uint32_t w = 0; w < 16; ++w) {
-            const uint32_t c = wsum[w], r = wsum[16 + w];
+        for (uint32_t w = 0; w < kTileWaves; ++w) {
+            const uint32_t c = wsum[w], r = wsum[kTileWaves + w];
             total += c;
             nruns += r;
             oc += w < wave ? c : 0u;
@@ -267,16 +273,16 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
             const uint32_t len = min(kSeg, total - s0);
             const uint32_t words = ((len + 63u) >> 6) * 2u;
             __syncthreads();  // runs written / previous segment done with the bitmap
-            for (uint32_t q = tid; q < words; q += 1024u) bits[q] = 0u;
+            for (uint32_t q = tid; q < words; q += kTileThreads) bits[q] = 0u;
             __syncthreads();
-            for (uint32_t k = tid; k < nruns; k += 1024u) {
+            for (uint32_t k = tid; k < nruns; k += kTileThreads) {
                 const uint32_t pos = roff[k] - s0;
                 if (pos < len) atomicOr(&bits[pos >> 5], 1u << (pos & 31u));
             }
             __syncthreads();
             const uint32_t nwin = (len + 63u) >> 6;
-            const uint32_t r0 = s0 + (nwin * wave / 16u) * 64u;
-            const uint32_t r1 = s0 + min(len, (nwin * (wave + 1u) / 16u) * 64u);
+            const uint32_t r0 = s0 + (nwin * wave / kTileWaves) * 64u;
+            const uint32_t r1 = s0 + min(len, (nwin * (wave + 1u) / kTileWaves) * 64u);
             if (r0 < r1)
                 splat_segment<S, 12>(seg, keys, roff, runs,
                                      reinterpret_cast<const uint64_t*>(bits), nruns, s0, r0, r1);
@@ -298,7 +304,7 @@ __device__ __forceinline__ void tile_split(const TileView& v, uint32_t t, uint32
 }
 
 template <int FOOT, int SHIFT>
-__global__ __launch_bounds__(1024) void tile_kernel(TileArgs a) {
+__global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a) {
     using Sh = TileShape<FOOT, SHIFT>;
     __shared__ uint64_t keys[Sh::S * Sh::S];
     __shared__ uint32_t col[Sh::kColLds];
@@ -400,7 +406,7 @@ __global__ __launch_bounds__(1024) void plan_kernel(TileArgs a) {
 // Persistent grid: each workgroup takes items (tile, piece j of k) until the
 // list is done; piece j covers bin workgroups [num_wg * j / k, num_wg * (j + 1) / k).
 template <int FOOT, int SHIFT>
-__global__ __launch_bounds__(1024) void tile_list_kernel(TileArgs a) {
+__global__ __launch_bounds__(kTileThreads) void tile_list_kernel(TileArgs a) {
     using Sh = TileShape<FOOT, SHIFT>;
     __shared__ uint64_t keys[Sh::S * Sh::S];
     __shared__ uint32_t col[Sh::kColLds];
@@ -421,7 +427,7 @@ __global__ __launch_bounds__(1024) void tile_list_kernel(TileArgs a) {
 }
 
 template <int FOOT, int SHIFT>
-__global__ __launch_bounds__(1024) void batch_tile_kernel(BatchTileArgs a) {
+__global__ __launch_bounds__(kTileThreads) void batch_tile_kernel(BatchTileArgs a) {
     using Sh = TileShape<FOOT, SHIFT>;
     __shared__ uint64_t keys[Sh::S * Sh::S];
     __shared__ uint32_t col[Sh::kColLds];
@@ -656,7 +662,7 @@ uint32_t batch_grid(uint32_t items, uint32_t grid_blocks) {
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits) {
     Launch l;
     l.func = footprint == 3 ? pick_tile<3>(shift, false) : pick_tile<1>(shift, false);
-    l.block = dim3(1024);
+    l.block = dim3(kTileThreads);
     l.grid = dim3((ntiles + 511u) / 512u * 512u * splits);  // whole runs of 8 XCDs x 64 tiles
     l.shared = 0;
     return l;
@@ -711,7 +717,7 @@ const void* pick_tile_list(int shift) {
 Launch tile_list_launch(int footprint, int shift, uint32_t grid_blocks) {
     Launch l;
     l.func = footprint == 3 ? pick_tile_list<3>(shift) : pick_tile_list<1>(shift);
-    l.block = dim3(1024);
+    l.block = dim3(kTileThreads);
     l.grid = dim3(grid_blocks);
     l.shared = 0;
     return l;
@@ -720,7 +726,7 @@ Launch tile_list_launch(int footprint, int shift, uint32_t grid_blocks) {
 Launch batch_tile_launch(int footprint, int shift, uint32_t items, uint32_t grid_blocks) {
     Launch l;
     l.func = footprint == 3 ? pick_tile<3>(shift, true) : pick_tile<1>(shift, true);
-    l.block = dim3(1024);
+    l.block = dim3(kTileThreads);
     l.grid = dim3(batch_grid(items, grid_blocks));
     l.shared = 0;
     return l;
