@@ -39,7 +39,9 @@ KERNEL_SOURCES = {
     "bin_kernel": ["mm_bin_plain.hip", "mm_bin_dev.h", "mm_device.h", "mm_internal.h"],
 }
 TRAFFIC = {
-    "bin_kernel": {"digest": "e71821ef203dbede", "fetch_kib": 98394.4, "write_kib": 335986.5,
+    "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
+                   "tuning": [2, 32, 8, 2, 1024, 0xFFFFFFFF],
+                   "digest": "e71821ef203dbede", "fetch_kib": 98394.4, "write_kib": 335986.5,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 POINT_BYTES = 24   # float3 read + write per point and frame
@@ -56,9 +58,12 @@ def kernel_digest(kernel: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, workload: str, tuning):
+    """HBM bytes per launch from the counters, for the workload, tuning and
+    kernel sources they were taken on; None otherwise."""
     e = TRAFFIC.get(kernel)
-    if not e or e["digest"] != kernel_digest(kernel):
+    if (not e or e["workload"] != workload or tuple(e["tuning"]) != tuple(tuning)
+            or e["digest"] != kernel_digest(kernel)):
         return None
     return (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"]) * 1024.0
 
@@ -549,6 +554,8 @@ def main() -> int:
     frame_bytes = point_bytes + PIXEL_BYTES * w * h
     splat_avg = float(np.mean(splat_ms))
     achieved = point_bytes / (splat_avg * 1e-3) / 1e9
+    workload = (f"3d-{args.dist}-2^{args.log2n}pts-{w}x{h}-orbit-1deg"
+                + (f"-{args.footprint}x{args.footprint}" if args.footprint != 1 else ""))
     out = {
         "metric": METRIC,
         "value": n * K / elapsed / 1e9,
@@ -562,8 +569,7 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"3d-{args.dist}-2^{args.log2n}pts-{w}x{h}-orbit-1deg"
-                               + (f"-{args.footprint}x{args.footprint}" if args.footprint != 1 else ""),
+        "config": {"workload": workload,
                    "points": n, "width": w, "height": h, "footprint": args.footprint,
                    "amplitude": 0.001,
                    "graph": ("bin of frame f beside the draw of frame f - 1 (two streams)"
@@ -577,7 +583,8 @@ def main() -> int:
         "rest_of_frame_ms": float(np.mean(resolve_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic("bin_kernel") if mode == "binned" else None,
+                     "traffic": (measured_traffic("bin_kernel", workload, tuning)
+                                 if mode == "binned" else None),
                      "kernel": ("bin_kernel (displace+project+tile sort)" if mode == "binned"
                                 else "point_kernel (displace+project+splat)"),
                      "bytes_per_launch": point_bytes},
