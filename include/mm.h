@@ -138,6 +138,28 @@ mm_status mm_render(mm_view view);
  * launch on the stream. Equivalent to mm_step then mm_render. */
 mm_status mm_step_render(mm_view view, uint32_t step);
 
+/* Colour of a view's points (section "Views": a colour property read per
+ * element, or through an index description into a table, as value mapping
+ * with a colormap; a default when the property is absent). */
+typedef struct {
+    mm_alloc palette;      /* RGBA8 entries (uint32 each, red in the low byte, stored
+                              as given, alpha included); NULL: the default colour,
+                              a hash of the point index with opaque alpha */
+    uint32_t palette_size; /* entries, >= 1; without indices, >= the view's points */
+    mm_alloc indices;      /* per-point unsigned palette index of index_size bytes;
+                              NULL: point i takes palette entry i */
+    uint32_t index_size;   /* 1, 2 or 4 */
+} mm_colour_desc;
+
+/* Sets the view's colour source for later frames (desc NULL: the default
+ * hash colour). A pixel's colour is that of the point that wins its depth
+ * test; an index at or past palette_size gives colour 0 (the point still
+ * hides what lies behind it). The view keeps the allocations in use (mm_free
+ * refuses them) until another colour source is set or the view is
+ * destroyed; their contents are read at every frame. Rebuilds the frame
+ * graph and synchronises. */
+mm_status mm_set_colour(mm_view view, const mm_colour_desc* desc);
+
 /* Frame overlap, the device form of the paper's ping-pong scheme (section
  * "Synchronization": one buffer is displayed while the other is written)
  * with the two sides unsynchronised (the study of section "Performance

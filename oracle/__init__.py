@@ -167,3 +167,32 @@ def render(pos: np.ndarray, seed: int, m, width: int, height: int,
     depth = new_depth(width, height)
     splat(pos, m, width, height, footprint, depth)
     return resolve(depth, seed).reshape(height, width)
+
+
+def palette_colours(keys: np.ndarray, palette: np.ndarray,
+                    indices: np.ndarray | None = None) -> np.ndarray:
+    """Colours of resolved keys under a palette (section "Views": a colour
+    property read per element, or through an index description into a
+    table). A pixel with no point is 0. Otherwise i is the winning point's
+    index (low word of its key); j = indices[i], or i without indices; the
+    colour is palette[j], or 0 when j is past the palette's end.
+    palette: uint32 RGBA8 entries; indices: unsigned integers per point."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    palette = np.asarray(palette, dtype=np.uint32)
+    out = np.zeros(keys.shape, dtype=np.uint32)
+    drawn = keys != EMPTY
+    i = (keys[drawn] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    j = np.asarray(indices)[i].astype(np.int64) if indices is not None else i
+    inside = j < palette.shape[0]
+    c = np.zeros(i.shape, dtype=np.uint32)
+    c[inside] = palette[j[inside]]
+    out[drawn] = c
+    return out
+
+
+def render_palette(pos: np.ndarray, m, width: int, height: int, footprint: int,
+                   palette: np.ndarray, indices: np.ndarray | None = None) -> np.ndarray:
+    """Splat without displacement, then the palette colours of the keys."""
+    depth = new_depth(width, height)
+    splat(pos, m, width, height, footprint, depth)
+    return palette_colours(depth, palette, indices).reshape(height, width)

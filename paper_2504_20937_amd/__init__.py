@@ -72,6 +72,15 @@ class mm_tuning(C.Structure):
                 ("piece_records", C.c_uint32)]
 
 
+class mm_colour_desc(C.Structure):
+    _fields_ = [
+        ("palette", C.c_void_p),
+        ("palette_size", C.c_uint32),
+        ("indices", C.c_void_p),
+        ("index_size", C.c_uint32),
+    ]
+
+
 class mm_cloud_desc(C.Structure):
     _fields_ = [
         ("position", C.c_void_p),
@@ -148,6 +157,7 @@ def _declare(L):
         "mm_render": ([_vp], _status),
         "mm_step_render": ([_vp, C.c_uint32], _status),
         "mm_set_frame_overlap": ([_vp, C.c_uint32], _status),
+        "mm_set_colour": ([_vp, C.POINTER(mm_colour_desc)], _status),
         "mm_flush_frame": ([_vp], _status),
         "mm_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
         "mm_read_frame": ([_vp, _vp, C.c_size_t], _status),
@@ -325,6 +335,18 @@ def mm_render(view: int) -> None:
 
 def mm_step_render(view: int, step: int) -> None:
     _check(lib().mm_step_render(view, step), "mm_step_render")
+
+
+def mm_set_colour(view: int, palette=None, palette_size: int = 0, indices=None,
+                  index_size: int = 0) -> None:
+    """Colour source of the view: palette (an mm_alloc of RGBA8 entries) read
+    through indices (an mm_alloc of index_size-byte integers) or by point
+    index; palette None restores the default hash colour."""
+    if palette is None:
+        _check(lib().mm_set_colour(view, None), "mm_set_colour")
+        return
+    d = mm_colour_desc(palette, palette_size, indices, index_size)
+    _check(lib().mm_set_colour(view, C.byref(d)), "mm_set_colour")
 
 
 def mm_set_frame_overlap(view: int, on: bool) -> None:

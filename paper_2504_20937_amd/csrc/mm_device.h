@@ -155,6 +155,23 @@ __device__ __forceinline__ uint32_t colour_of(uint64_t key, uint32_t seed_lo, ui
     return r.x | 0xFF000000u;
 }
 
+// Colour of a resolved key under the view's palette: the hash colour when it
+// has none; else the table entry of the winning point (through its index
+// when the palette has an index buffer), 0 past the table's end.
+__device__ __forceinline__ uint32_t pixel_colour(uint64_t key, uint32_t seed_lo, uint32_t seed_hi,
+                                                 const Palette& p) {
+    if (!p.table) return colour_of(key, seed_lo, seed_hi);
+    if (key == kEmptyKey) return 0u;
+    const uint32_t i = static_cast<uint32_t>(key);
+    uint32_t j = i;
+    if (p.index) {
+        if (p.index_size == 1) j = static_cast<const uint8_t*>(p.index)[i];
+        else if (p.index_size == 2) j = static_cast<const uint16_t*>(p.index)[i];
+        else j = static_cast<const uint32_t*>(p.index)[i];
+    }
+    return j < p.size ? p.table[j] : 0u;
+}
+
 __device__ __forceinline__ void atomic_min_global(uint64_t* slot, uint64_t key) {
     __hip_atomic_fetch_min(reinterpret_cast<unsigned long long*>(slot),
                            static_cast<unsigned long long>(key), __ATOMIC_RELAXED,

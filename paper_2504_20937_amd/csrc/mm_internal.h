@@ -38,11 +38,23 @@ struct PointArgs {
     uint64_t* depth;    // width * height keys
 };
 
+// Colour source of a view: the per-point hash (table == nullptr), or RGBA8
+// table entries, taken through a per-point index buffer of index_size (1, 2
+// or 4) byte unsigned integers, or by point index when index == nullptr. An
+// index past the table gives colour 0.
+struct Palette {
+    const uint32_t* table;
+    const void* index;
+    uint32_t size;
+    uint32_t index_size;
+};
+
 struct ResolveArgs {
     uint64_t* depth;    // read, then reset to empty
     uint32_t* colour;
     uint64_t npix;      // even
     uint32_t seed_lo, seed_hi;
+    Palette pal;
 };
 
 // Binned splat, bin pass side of one view.
@@ -72,6 +84,7 @@ struct TileView {
     uint32_t full_clear; // 1: clear every tile not drawn this frame (the frame buffer
                          // holds no earlier frame); 0: only tiles drawn last frame
     uint32_t seed_lo, seed_hi;
+    Palette pal;
 };
 
 // Binned splat of one cloud into one view.

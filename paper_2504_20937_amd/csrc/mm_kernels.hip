@@ -61,8 +61,8 @@ __global__ __launch_bounds__(256) void resolve_kernel(ResolveArgs a) {
     if (2 * j >= a.npix) return;
     ulonglong2* d2 = reinterpret_cast<ulonglong2*>(a.depth);
     const ulonglong2 k = d2[j];
-    const uint2 c = make_uint2(colour_of(k.x, a.seed_lo, a.seed_hi),
-                               colour_of(k.y, a.seed_lo, a.seed_hi));
+    const uint2 c = make_uint2(pixel_colour(k.x, a.seed_lo, a.seed_hi, a.pal),
+                               pixel_colour(k.y, a.seed_lo, a.seed_hi, a.pal));
     reinterpret_cast<uint2*>(a.colour)[j] = c;
     d2[j] = make_ulonglong2(kEmptyKey, kEmptyKey);
 }

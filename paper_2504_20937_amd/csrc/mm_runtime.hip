@@ -35,6 +35,10 @@ struct FrameGraph {
 struct mm_view_s {
     mm_instance inst;
     mm_alloc position;
+    // colour source (mm_set_colour): palette table and optional index buffer
+    mm_alloc pal_table = nullptr;
+    mm_alloc pal_index = nullptr;
+    mm::Palette pal{};
     mm_view_desc desc;
     mm_tuning tuning{};
     uint32_t* colour = nullptr;
@@ -249,7 +253,8 @@ mm_status setup_splat(mm_view v) {
         if (e == hipSuccess) e = mm::launch_fill(v->depth, npix, mm::kEmptyKey, inst->stream);
         if (e != hipSuccess) return hip_fail(e, "direct splat buffers");
         fill_point_args(v);
-        v->rargs = mm::ResolveArgs{v->depth, v->colour, npix, v->args.c.seed_lo, v->args.c.seed_hi};
+        v->rargs = mm::ResolveArgs{v->depth, v->colour, npix, v->args.c.seed_lo, v->args.c.seed_hi,
+                                   v->pal};
         v->nodes.push_back(mm::point_launch(dim, foot, wrap, mm::kDisplaceRender, v->args.c.n));
         v->nodes.push_back(mm::resolve_launch(npix));
     } else {
@@ -316,6 +321,7 @@ mm_status setup_splat(mm_view v) {
         t.v.piece_first = v->piece_first;
         t.v.seed_lo = v->args.c.seed_lo;
         t.v.seed_hi = v->args.c.seed_hi;
+        t.v.pal = v->pal;
         t.stamp_in = v->active + v->ntiles;
         t.points_per_wg = static_cast<uint32_t>(P);
         t.tile_total = v->tile_total;
@@ -714,6 +720,8 @@ mm_status mm_destroy_view(mm_view v) {
     MM_HIP(hipStreamSynchronize(inst->stream));
     destroy_view_resources(v);
     v->position->users--;
+    if (v->pal_table) v->pal_table->users--;
+    if (v->pal_index) v->pal_index->users--;
     inst->views.erase(v);
     delete v;
     return MM_OK;
@@ -884,6 +892,54 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
     MM_HIP(hipGraphExecKernelNodeSetParams(v->plain.exec, v->plain.first, &pp));
     MM_HIP(hipGraphLaunch(v->plain.exec, v->inst->stream));
     return MM_OK;
+}
+
+mm_status mm_set_colour(mm_view v, const mm_colour_desc* d) {
+    if (!v) return fail(MM_ERR_INVALID_ARG, "set_colour: null view");
+    mm_instance inst = v->inst;
+    mm::Palette pal{};
+    mm_alloc table = nullptr, index = nullptr;
+    if (d && d->palette) {
+        table = d->palette;
+        if (!inst->allocs.count(table))
+            return fail(MM_ERR_INVALID_ARG, "set_colour: palette is not an alloc of this instance");
+        if (d->palette_size < 1 || d->palette_size > table->bytes / 4)
+            return fail(MM_ERR_INVALID_ARG, "set_colour: %u palette entries do not fit the %zu-byte alloc",
+                        d->palette_size, table->bytes);
+        const uint64_t n = v->desc.element_count;
+        if (d->indices) {
+            index = d->indices;
+            if (!inst->allocs.count(index))
+                return fail(MM_ERR_INVALID_ARG, "set_colour: indices is not an alloc of this instance");
+            if (d->index_size != 1 && d->index_size != 2 && d->index_size != 4)
+                return fail(MM_ERR_INVALID_ARG, "set_colour: index_size %u is not 1, 2 or 4", d->index_size);
+            if (n > index->bytes / d->index_size)
+                return fail(MM_ERR_INVALID_ARG, "set_colour: %llu indices of %u B exceed the %zu-byte alloc",
+                            (unsigned long long)n, d->index_size, index->bytes);
+        } else if (d->palette_size < n) {
+            return fail(MM_ERR_INVALID_ARG, "set_colour: per-point palette of %u entries for %llu points",
+                        d->palette_size, (unsigned long long)n);
+        }
+        pal.table = static_cast<const uint32_t*>(table->ptr);
+        pal.index = index ? index->ptr : nullptr;
+        pal.size = d->palette_size;
+        pal.index_size = index ? d->index_size : 0u;
+    }
+    DeviceGuard guard(inst->device);
+    MM_TRY(flush_frame(v));
+    MM_HIP(hipStreamSynchronize(inst->stream));
+    if (v->pal_table) v->pal_table->users--;
+    if (v->pal_index) v->pal_index->users--;
+    v->pal_table = table;
+    v->pal_index = index;
+    if (table) table->users++;
+    if (index) index->users++;
+    v->pal = pal;
+    if (!v->plain.exec) return MM_OK;  // applied by the next successful mm_set_tuning
+    teardown_splat(v);
+    const mm_status st = setup_splat(v);
+    if (st != MM_OK) teardown_splat(v);
+    return st;
 }
 
 mm_status mm_set_frame_overlap(mm_view v, uint32_t on) {

@@ -491,7 +491,7 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
         const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
         if (lx >= wt || ly >= ht) continue;
         if constexpr (FOOT == 1) {
-            out[static_cast<uint64_t>(ly) * v.width + lx] = colour_of(key_at(q), v.seed_lo, v.seed_hi);
+            out[static_cast<uint64_t>(ly) * v.width + lx] = pixel_colour(key_at(q), v.seed_lo, v.seed_hi, v.pal);
         } else {
             const uint64_t k = key_at((ly + 1) * A + lx + 1);
             if (lx == 0 || ly == 0 || lx == S - 1 || ly == S - 1) {
@@ -501,7 +501,7 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
                 if (lx == 0) bd[2 * S + ly] = k;
                 if (lx == S - 1) bd[3 * S + ly] = k;
             } else {
-                out[static_cast<uint64_t>(ly) * v.width + lx] = colour_of(k, v.seed_lo, v.seed_hi);
+                out[static_cast<uint64_t>(ly) * v.width + lx] = pixel_colour(k, v.seed_lo, v.seed_hi, v.pal);
             }
         }
     }
@@ -586,7 +586,7 @@ __device__ __forceinline__ void seam_tile(const TileView& v, uint32_t t, uint32_
                                            ring_index<S>(static_cast<uint32_t>(ax), static_cast<uint32_t>(ay))];
                 k = p < k ? p : k;
             }
-        out[static_cast<uint64_t>(ly) * v.width + lx] = colour_of(k, v.seed_lo, v.seed_hi);
+        out[static_cast<uint64_t>(ly) * v.width + lx] = pixel_colour(k, v.seed_lo, v.seed_hi, v.pal);
     }
 }
 

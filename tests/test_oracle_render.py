@@ -253,3 +253,51 @@ def test_step_render_is_displace_then_render():
     oracle.displace(b, 0, 4, 0.005, True)
     assert np.array_equal(a, b)
     assert np.array_equal(frame, oracle.render(b, 0, synth.IDENTITY, w, h, 1))
+
+
+def test_palette_of_hash_colours_is_the_default_render():
+    """Special case that reduces to the pinned hash colour: a per-point
+    palette holding each point's hash colour gives the default frame."""
+    w, h = 96, 64
+    pos = synth.uniform_cube(4000, 3)
+    m = synth.orbit_camera(40, w, h)
+    pal = np.array([oracle.colour(i, 5) for i in range(pos.shape[0])], dtype=np.uint32)
+    assert np.array_equal(oracle.render_palette(pos, m, w, h, 3, pal),
+                          oracle.render(pos, 5, m, w, h, 3))
+    # the same through an identity index buffer of each width
+    for dt in (np.uint16, np.uint32):
+        idx = np.arange(pos.shape[0], dtype=dt)
+        assert np.array_equal(oracle.render_palette(pos, m, w, h, 3, pal, idx),
+                              oracle.render(pos, 5, m, w, h, 3))
+
+
+def test_palette_single_entry_covers_exactly_the_drawn_pixels():
+    w, h = 80, 60
+    pos = synth.gaussian_mixture(3000, 1, sigma=0.05)
+    m = synth.orbit_camera(10, w, h)
+    idx = np.zeros(pos.shape[0], dtype=np.uint8)
+    got = oracle.render_palette(pos, m, w, h, 1, np.array([0x11223344], np.uint32), idx)
+    drawn = oracle.render(pos, 0, m, w, h, 1) != 0  # hash colours are never 0 (opaque)
+    assert np.all(got[drawn] == 0x11223344) and np.all(got[~drawn] == 0)
+
+
+def test_palette_brute_force_with_indices_past_the_end():
+    """Gather form: per pixel the winning point by brute force, then its
+    palette entry through its index; indices at or past the end give 0."""
+    for seed in range(200):
+        rng = np.random.default_rng(seed)
+        n = int(rng.integers(1, 33))
+        w, h = 2 * int(rng.integers(1, 9)), 2 * int(rng.integers(1, 9))
+        footprint = 1 if seed % 2 == 0 else 3
+        pos = (0.5 + 0.2 * rng.standard_normal((n, 3))).astype(np.float32)
+        m = synth.orbit_camera(int(rng.integers(0, 360)), w, h)
+        pal = rng.integers(1, 2**32, size=int(rng.integers(1, 9)), dtype=np.uint64).astype(np.uint32)
+        idx = rng.integers(0, pal.shape[0] + 3, size=n).astype(np.uint8)
+        keys = _gather(pos, m, w, h, footprint)
+        want = np.zeros(w * h, dtype=np.uint32)
+        for q in range(w * h):
+            if keys[q] != EMPTY:
+                j = int(idx[int(keys[q]) & 0xFFFFFFFF])
+                want[q] = pal[j] if j < pal.shape[0] else 0
+        got = oracle.render_palette(pos, m, w, h, footprint, pal, idx)
+        assert np.array_equal(got.reshape(-1), want), seed
