@@ -41,7 +41,7 @@ KERNEL_SOURCES = {
 TRAFFIC = {
     "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
                    "tuning": [2, 32, 8, 2, 1024, 0xFFFFFFFF],
-                   "digest": "e71821ef203dbede", "fetch_kib": 98394.4, "write_kib": 335986.5,
+                   "digest": "abd68e1476d92b3d", "fetch_kib": 98394.5, "write_kib": 336028.7,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 POINT_BYTES = 24   # float3 read + write per point and frame
