@@ -220,8 +220,9 @@ typedef struct {
                                    load: every tile is cut into pieces of about this
                                    many records (at least points / 65535), taken by a
                                    persistent grid; MM_PIECES_STATIC: `splits`
-                                   workgroups per tile; 0 = auto (static below
-                                   8192 bin workgroups, else balanced by load) */
+                                   workgroups per tile; 0 = auto (static when
+                                   splits is set or below 8192 bin workgroups,
+                                   else balanced by load) */
 } mm_tuning;
 
 #define MM_PIECES_STATIC 0xFFFFFFFFu

@@ -200,7 +200,7 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
     if (out.piece_records == 0) {
         const uint64_t P = static_cast<uint64_t>(out.bin_threads) * out.points_per_thread;
         const uint64_t wgs = (d.element_count + P - 1) / P;
-        if (wgs < 8192) {
+        if (wgs < 8192 || out.splits != 0) {  // explicit splits ask for the static pass
             out.piece_records = MM_PIECES_STATIC;
         } else {
             const uint64_t r = (d.element_count / 1024 + 1023) / 1024 * 1024;
