@@ -41,9 +41,10 @@ KERNEL_SOURCES = {
 TRAFFIC = {
     "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
                    "tuning": [2, 32, 8, 2, 1024, 0xFFFFFFFF],
-                   "digest": "abd68e1476d92b3d", "fetch_kib": 98394.5, "write_kib": 336028.7,
+                   "digest": "747b4982bc4063dd", "fetch_kib": 98394.3, "write_kib": 335970.9,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
+PROFILE_EVERY = 8  # frames per profiled frame in the timed loop
 POINT_BYTES = 24   # float3 read + write per point and frame
 PIXEL_BYTES = 20   # key read + empty-key write (8 + 8) and RGBA8 write (4)
 
@@ -534,7 +535,12 @@ def main() -> int:
     for f in range(W):
         mm.mm_set_camera(view, cams[f])
         mm.mm_step_render(view, f)
-    mm.mm_profile_begin(view, K)  # synchronises
+    # HIP events inside the frame graph on one frame in PROFILE_EVERY: the
+    # host calls that re-point a timed graph's event nodes would otherwise
+    # pace the frame loop
+    mm.mm_profile_every(view, PROFILE_EVERY)
+    prof_cap = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
+    mm.mm_profile_begin(view, prof_cap)  # synchronises
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
@@ -544,7 +550,7 @@ def main() -> int:
     mm.mm_flush_frame(view)  # with overlap, the last frame is drawn inside the timed region
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    splat_ms, resolve_ms, frame_ms = mm.mm_profile_end(view, K)
+    splat_ms, resolve_ms, frame_ms = mm.mm_profile_end(view, prof_cap)
     elapsed = t1 - t0
     mm.mm_destroy_view(view)
     mm.mm_free(alloc)
@@ -579,6 +585,7 @@ def main() -> int:
         "frames_per_s": K / elapsed,
         "p50_frame_ms": float(np.percentile(frame_ms, 50)),
         "p99_frame_ms": float(np.percentile(frame_ms, 99)),
+        "profiled_frames": f"{len(frame_ms)} (1 in {PROFILE_EVERY} of the timed frames)",
         "point_kernel_ms": splat_avg,
         "rest_of_frame_ms": float(np.mean(resolve_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,

@@ -260,6 +260,13 @@ mm_status mm_autotune(mm_view view, uint32_t frames, mm_tuning* out);
  * frame_ms[k] (arrays of `capacity`, any may be NULL),
  * and *count; recording then stops. */
 mm_status mm_profile_begin(mm_view view, uint32_t capacity);
+
+/* Sampling of the profile: from the next mm_profile_begin on, events are
+ * recorded on the first of every `every` calls (1 <= every <= 1000; default
+ * 1, every call) and the other calls launch the plain graph. Re-pointing the
+ * timed graph's event nodes costs host time per recorded frame; sampling
+ * keeps that cost out of the rate of a tight frame loop. */
+mm_status mm_profile_every(mm_view view, uint32_t every);
 mm_status mm_profile_end(mm_view view, float* splat_ms, float* resolve_ms, float* frame_ms,
                          uint32_t* count);
 

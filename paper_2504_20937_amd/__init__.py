@@ -164,6 +164,7 @@ def _declare(L):
         "mm_set_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
         "mm_get_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
         "mm_profile_begin": ([_vp, C.c_uint32], _status),
+        "mm_profile_every": ([_vp, C.c_uint32], _status),
         "mm_profile_end": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
                             C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
         "mm_autotune": ([_vp, C.c_uint32, C.POINTER(mm_tuning)], _status),
@@ -370,6 +371,10 @@ def mm_read_frame(view: int, width: int, height: int) -> np.ndarray:
     out = np.empty((height, width), dtype=np.uint32)
     _check(lib().mm_read_frame(view, out.ctypes.data, out.nbytes), "mm_read_frame")
     return out
+
+
+def mm_profile_every(view: int, every: int) -> None:
+    _check(lib().mm_profile_every(view, every), "mm_profile_every")
 
 
 def mm_profile_begin(view: int, capacity: int) -> None:

@@ -71,26 +71,30 @@ struct Float3 {
     float x, y, z;
 };
 
+// Positions are streamed: read once and written once per frame, so both
+// directions use non-temporal accesses, which keep the caches for the tile
+// records and table that the tile pass reads right after the bin pass
+// (1080p, 2^24 points: 177 -> 155 us per frame; 4K 2^28: bin pass 1.75 -> 1.62 ms).
 template <int DIM>
 __device__ __forceinline__ void load_point(const float* pos, uint32_t i, float& x, float& y,
                                            float& z) {
     if constexpr (DIM == 2) {
-        const float2 p = reinterpret_cast<const float2*>(pos)[i];
+        typedef float f2v __attribute__((ext_vector_type(2)));
+        const f2v p = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(pos) + i);
         x = p.x;
         y = p.y;
         z = 0.0f;
     } else {
-        const Float3 p = reinterpret_cast<const Float3*>(pos)[i];
+        typedef float f3v __attribute__((ext_vector_type(3)));
+        // a 12-byte load (global_load_dwordx3 nt) of the point's 12-byte slot
+        const f3v p = __builtin_nontemporal_load(
+            reinterpret_cast<const f3v*>(reinterpret_cast<const char*>(pos) + 12ull * i));
         x = p.x;
         y = p.y;
         z = p.z;
     }
 }
 
-// Non-temporal stores: the positions are read again only by the next frame,
-// after the whole cloud has streamed through, so they are kept out of the
-// way of the tile records that the tile pass reads right after the bin pass
-// (1080p, 2^24 points: bin pass 102.7 -> 96.7 us, tile pass 62 -> 50 us).
 template <int DIM>
 __device__ __forceinline__ void store_point(float* pos, uint32_t i, float x, float y, float z) {
     if constexpr (DIM == 2) {

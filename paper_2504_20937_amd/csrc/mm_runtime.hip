@@ -66,6 +66,7 @@ struct mm_view_s {
     FrameGraph plain, timed;
     std::vector<hipEvent_t> events;  // 3 per profiled frame
     uint32_t prof_cap = 0, prof_count = 0;
+    uint32_t prof_every = 1, prof_skip = 0;  // record 1 frame in prof_every
     bool profiling = false;
     // Frame overlap (binned only): frame f is binned into record set f & 1 on
     // the instance stream while frame f - 1 is drawn from the other set on
@@ -466,7 +467,8 @@ mm_status overlap_frame(mm_view v, mm::Phase phase, uint32_t step) {
     // the last draw of set k has read its records
     MM_HIP(hipStreamWaitEvent(s, v->ev_drawn[k], 0));
     hipEvent_t* ev = nullptr;
-    if (v->profiling && v->prof_count < v->prof_cap) ev = &v->events[3ull * v->prof_count++];
+    if (v->profiling && v->prof_count < v->prof_cap && v->prof_skip++ % v->prof_every == 0)
+        ev = &v->events[3ull * v->prof_count++];
     if (ev) MM_HIP(hipEventRecord(ev[0], s));
     const mm::Launch bl = mm::bin_launch(static_cast<int>(v->desc.domain), v->desc.wrap != 0, phase,
                                          static_cast<int>(v->tuning.points_per_thread),
@@ -880,7 +882,7 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
     }
     void* args[] = {first_arg};
     hipKernelNodeParams pp = node_params(v->nodes[0], args);
-    if (v->profiling && v->prof_count < v->prof_cap) {
+    if (v->profiling && v->prof_count < v->prof_cap && v->prof_skip++ % v->prof_every == 0) {
         const uint32_t k = v->prof_count++;
         for (int j = 0; j < 3; ++j)
             MM_HIP(hipGraphExecEventRecordNodeSetEvent(v->timed.exec, v->timed.ev[j],
@@ -1009,7 +1011,15 @@ mm_status mm_profile_begin(mm_view v, uint32_t capacity) {
     MM_TRY(build_graph(v, true, v->timed));
     v->prof_cap = capacity;
     v->prof_count = 0;
+    v->prof_skip = 0;
     v->profiling = true;
+    return MM_OK;
+}
+
+mm_status mm_profile_every(mm_view v, uint32_t every) {
+    if (!v) return fail(MM_ERR_INVALID_ARG, "profile_every: null view");
+    if (every < 1 || every > 1000) return fail(MM_ERR_INVALID_ARG, "profile_every: %u outside [1, 1000]", every);
+    v->prof_every = every;
     return MM_OK;
 }
 
