@@ -42,6 +42,7 @@ typedef struct mm_alloc_s* mm_alloc;
 typedef struct mm_view_s* mm_view;
 typedef struct mm_batch_s* mm_batch;
 typedef struct mm_server_s* mm_server;
+typedef struct mm_grid_s* mm_grid;
 
 typedef int32_t mm_status;
 #define MM_OK 0
@@ -269,6 +270,37 @@ mm_status mm_profile_begin(mm_view view, uint32_t capacity);
 mm_status mm_profile_every(mm_view view, uint32_t every);
 mm_status mm_profile_end(mm_view view, float* splat_ms, float* resolve_ms, float* frame_ms,
                          uint32_t* count);
+
+/* ------------------------------------------------------- structured grids
+ * The paper's voxel view of a 2D structured domain (section "Potts model":
+ * an L x L lattice drawn from the simulation's cell array, its states mapped
+ * to colours): a cols x rows lattice of cells fills the screen, and the
+ * pixel whose centre lies in cell (cx, cy) takes the palette entry of that
+ * cell's value. Cell column of pixel column px: floor((px + 1/2) * cols /
+ * width); cell row of pixel row py (row 0 at the top): floor((height - 1 -
+ * py + 1/2) * rows / height), so cell row 0 is the bottom row, as y points
+ * up in the point views. A value at or past palette_size draws 0. */
+typedef struct {
+    uint32_t cols, rows;    /* lattice cells, each in [1, 65536] */
+    uint32_t width, height; /* screen, each even and in [2, 16384] */
+    mm_alloc palette;       /* RGBA8 entries (uint32, stored as given) */
+    uint32_t palette_size;  /* >= 1 */
+    mm_alloc indices;       /* cols * rows unsigned cell values of index_size bytes,
+                               row-major from the bottom row; read at every render */
+    uint32_t index_size;    /* 1, 2 or 4 */
+} mm_grid_desc;
+
+/* Creates a grid view with a zeroed RGBA8 frame of its own; it keeps both
+ * allocations in use until destroyed. */
+mm_status mm_create_grid(mm_instance inst, const mm_grid_desc* desc, mm_grid* out);
+/* Frees the frame after the instance stream has drained. */
+mm_status mm_destroy_grid(mm_grid grid);
+/* Draws the current cell values into the frame (one kernel on the instance
+ * stream; no host synchronisation). */
+mm_status mm_grid_render(mm_grid grid);
+mm_status mm_grid_frame_device_ptr(mm_grid grid, const uint32_t** dev_rgba);
+/* Copies the frame to host memory (bytes >= width * height * 4); synchronises. */
+mm_status mm_grid_read_frame(mm_grid grid, void* host_rgba, size_t bytes);
 
 /* ----------------------------------------------------------------- batches
  * Many point clouds, each drawn into one or more views, rendered together

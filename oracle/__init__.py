@@ -196,3 +196,23 @@ def render_palette(pos: np.ndarray, m, width: int, height: int, footprint: int,
     depth = new_depth(width, height)
     splat(pos, m, width, height, footprint, depth)
     return palette_colours(depth, palette, indices).reshape(height, width)
+
+
+def render_grid(cols: int, rows: int, width: int, height: int, palette: np.ndarray,
+                cells: np.ndarray) -> np.ndarray:
+    """Structured-grid frame (the voxel view of a 2D lattice, section "Potts
+    model": cell states drawn through a colormap). Pixel (px, py), row 0 at
+    the top, shows the cell whose area holds the pixel centre: column
+    floor((px + 1/2) cols / width), row floor((height - 1 - py + 1/2) rows /
+    height) counted from the bottom; colour palette[value], or 0 when the
+    value is past the palette. cells: cols * rows values, row-major from the
+    bottom row. Returns (height, width) uint32."""
+    palette = np.asarray(palette, dtype=np.uint32)
+    cells = np.asarray(cells).reshape(-1).astype(np.int64)
+    px = np.arange(width, dtype=np.int64)
+    py = np.arange(height, dtype=np.int64)
+    cx = (2 * px + 1) * cols // (2 * width)
+    cy = (2 * (height - 1 - py) + 1) * rows // (2 * height)
+    v = cells[cy[:, None] * cols + cx[None, :]]
+    inside = v < palette.shape[0]
+    return np.where(inside, palette[np.where(inside, v, 0)], 0).astype(np.uint32)

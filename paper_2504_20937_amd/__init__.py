@@ -81,6 +81,15 @@ class mm_colour_desc(C.Structure):
     ]
 
 
+class mm_grid_desc(C.Structure):
+    _fields_ = [
+        ("cols", C.c_uint32), ("rows", C.c_uint32),
+        ("width", C.c_uint32), ("height", C.c_uint32),
+        ("palette", C.c_void_p), ("palette_size", C.c_uint32),
+        ("indices", C.c_void_p), ("index_size", C.c_uint32),
+    ]
+
+
 class mm_cloud_desc(C.Structure):
     _fields_ = [
         ("position", C.c_void_p),
@@ -158,6 +167,11 @@ def _declare(L):
         "mm_step_render": ([_vp, C.c_uint32], _status),
         "mm_set_frame_overlap": ([_vp, C.c_uint32], _status),
         "mm_set_colour": ([_vp, C.POINTER(mm_colour_desc)], _status),
+        "mm_create_grid": ([_vp, C.POINTER(mm_grid_desc), C.POINTER(_vp)], _status),
+        "mm_destroy_grid": ([_vp], _status),
+        "mm_grid_render": ([_vp], _status),
+        "mm_grid_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
+        "mm_grid_read_frame": ([_vp, _vp, C.c_size_t], _status),
         "mm_flush_frame": ([_vp], _status),
         "mm_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
         "mm_read_frame": ([_vp, _vp, C.c_size_t], _status),
@@ -348,6 +362,36 @@ def mm_set_colour(view: int, palette=None, palette_size: int = 0, indices=None,
         return
     d = mm_colour_desc(palette, palette_size, indices, index_size)
     _check(lib().mm_set_colour(view, C.byref(d)), "mm_set_colour")
+
+
+def mm_create_grid(inst: int, cols: int, rows: int, width: int, height: int, palette,
+                   palette_size: int, indices, index_size: int) -> int:
+    """Structured-grid view: a cols x rows lattice of cell values (indices, an
+    mm_alloc) drawn through palette (an mm_alloc of RGBA8 entries)."""
+    d = mm_grid_desc(cols, rows, width, height, palette, palette_size, indices, index_size)
+    out = _vp()
+    _check(lib().mm_create_grid(inst, C.byref(d), C.byref(out)), "mm_create_grid")
+    return out.value
+
+
+def mm_destroy_grid(grid: int) -> None:
+    _check(lib().mm_destroy_grid(grid), "mm_destroy_grid")
+
+
+def mm_grid_render(grid: int) -> None:
+    _check(lib().mm_grid_render(grid), "mm_grid_render")
+
+
+def mm_grid_frame_device_ptr(grid: int) -> int:
+    out = _vp()
+    _check(lib().mm_grid_frame_device_ptr(grid, C.byref(out)), "mm_grid_frame_device_ptr")
+    return out.value
+
+
+def mm_grid_read_frame(grid: int, width: int, height: int) -> np.ndarray:
+    out = np.empty((height, width), dtype=np.uint32)
+    _check(lib().mm_grid_read_frame(grid, out.ctypes.data, out.nbytes), "mm_grid_read_frame")
+    return out
 
 
 def mm_set_frame_overlap(view: int, on: bool) -> None:

@@ -31,6 +31,7 @@ struct mm_instance_s {
     std::set<mm_view> views;
     std::set<mm_batch> batches;
     std::set<mm_server> servers;
+    std::set<mm_grid> grids;
 };
 
 namespace mmh {

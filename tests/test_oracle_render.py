@@ -301,3 +301,33 @@ def test_palette_brute_force_with_indices_past_the_end():
                 want[q] = pal[j] if j < pal.shape[0] else 0
         got = oracle.render_palette(pos, m, w, h, footprint, pal, idx)
         assert np.array_equal(got.reshape(-1), want), seed
+
+
+def test_grid_one_pixel_per_cell_is_the_flipped_lattice():
+    """Closed form: with one pixel per cell the frame is the lattice of
+    palette colours with its rows flipped (cell row 0 at the bottom)."""
+    rng = np.random.default_rng(0)
+    cols, rows = 12, 8
+    pal = rng.integers(0, 2**32, 10, dtype=np.uint64).astype(np.uint32)
+    cells = rng.integers(0, 12, cols * rows).astype(np.uint16)  # 10, 11 past the palette
+    want = np.where(cells < 10, pal[np.minimum(cells, 9)], 0).astype(np.uint32).reshape(rows, cols)[::-1]
+    assert np.array_equal(oracle.render_grid(cols, rows, cols, rows, pal, cells), want)
+
+
+def test_grid_integer_magnification_replicates_cells():
+    rng = np.random.default_rng(1)
+    cols, rows, k = 6, 4, 3
+    pal = rng.integers(0, 2**32, 8, dtype=np.uint64).astype(np.uint32)
+    cells = rng.integers(0, 8, cols * rows).astype(np.uint8)
+    base = oracle.render_grid(cols, rows, cols, rows, pal, cells)
+    want = np.repeat(np.repeat(base, k, axis=0), k, axis=1)
+    assert np.array_equal(oracle.render_grid(cols, rows, k * cols, k * rows, pal, cells), want)
+
+
+def test_grid_cell_of_pixel_centre_in_float64():
+    """The integer cell rule equals the cell holding the pixel centre,
+    computed in float64 (exact at these sizes), for non-divisible sizes."""
+    for cols, width in [(7, 10), (10, 7), (1, 2), (33, 64), (64, 34), (5, 2)]:
+        for px in range(width):
+            centre = (px + 0.5) * cols / width
+            assert (2 * px + 1) * cols // (2 * width) == int(np.floor(centre))
