@@ -367,7 +367,9 @@ def bench_grid(args) -> dict:
     rng = np.random.default_rng(0)
     pal_t = torch.from_numpy(rng.integers(0, 2**32, 256, dtype=np.uint64).astype(np.uint32)).cuda()
     cells_t = torch.from_numpy(rng.integers(0, 256, L * L, dtype=np.uint8)).cuda()
-    stream = torch.cuda.current_stream()
+    # an explicit stream: the instance launches on it and the events time it
+    # (torch's default stream handle is null, for which an instance makes its own)
+    stream = torch.cuda.Stream()
     inst = mm.mm_create_instance(0, stream.cuda_stream)
     pal_a = mm.mm_alloc_wrap(inst, pal_t.data_ptr(), pal_t.numel() * 4)
     cells_a = mm.mm_alloc_wrap(inst, cells_t.data_ptr(), cells_t.numel())
@@ -397,9 +399,59 @@ def bench_grid(args) -> dict:
         "gpu_ms_per_frame": gpu_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "grid_kernel",
-                     "bytes_per_launch": bytes_per_frame,
-                     "note": "frame and lattice stay in the 256 MB Infinity Cache across renders, "
-                             "so the rate can exceed the HBM peak"},
+                     "bytes_per_launch": bytes_per_frame},
+    }
+
+
+def bench_edges(args) -> dict:
+    """Edges view: a 1024 x 1024 vertex lattice jittered in 2D and cut into
+    two triangles per cell (about 2.1 M triangles, 6.3 M edges, like the
+    paper's Delaunay edge views), drawn at the given screen size."""
+    import torch
+
+    import paper_2504_20937_amd as mm
+
+    L = 1024
+    w, h = args.width, args.height
+    K, W = args.steps, args.warmup
+    rng = np.random.default_rng(0)
+    g = (np.arange(L, dtype=np.float64) + 0.5) / L * 2.0 - 1.0
+    xy = np.stack(np.meshgrid(g, g, indexing="xy"), axis=-1).reshape(-1, 2)
+    pos = (xy + rng.uniform(-0.3, 0.3, xy.shape) * (2.0 / L)).astype(np.float32)
+    v = np.arange(L * L, dtype=np.uint32).reshape(L, L)
+    a, b, c, d = v[:-1, :-1], v[:-1, 1:], v[1:, :-1], v[1:, 1:]
+    tri = np.concatenate([np.stack([a, b, d], -1).reshape(-1, 3),
+                          np.stack([a, d, c], -1).reshape(-1, 3)]).reshape(-1)
+    stream = torch.cuda.Stream()  # explicit, so the events time the instance's stream
+    inst = mm.mm_create_instance(0, stream.cuda_stream)
+    pos_t = torch.from_numpy(pos).cuda()
+    tri_t = torch.from_numpy(tri.view(np.int32)).cuda()
+    pa = mm.mm_alloc_wrap(inst, pos_t.data_ptr(), pos_t.numel() * 4)
+    ta = mm.mm_alloc_wrap(inst, tri_t.data_ptr(), tri_t.numel() * 4)
+    ntri = tri.shape[0] // 3
+    e = mm.mm_create_edges(inst, pa, L * L, 2, ta, ntri, 3, w, h, 0)
+    for _ in range(W):
+        mm.mm_edges_render(e)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(K):
+        mm.mm_edges_render(e)
+    end.record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    gpu_ms = start.elapsed_time(end) / K
+    mm.mm_destroy_edges(e)
+    mm.mm_destroy_instance(inst)
+    return {
+        "metric": "edges view: frames/s and Gedges/s, 1024^2-vertex triangulated lattice, 2D",
+        "value": K / elapsed, "unit": "frames/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"edges-lattice-1024^2-2d-{w}x{h}", "vertices": L * L,
+                   "triangles": ntri, "edges": 3 * ntri, "width": w, "height": h},
+        "gpu_ms_per_frame": gpu_ms, "Gedges_per_s": 3 * ntri / (gpu_ms * 1e-3) / 1e9,
     }
 
 
@@ -512,7 +564,7 @@ def main() -> int:
     ap.add_argument("--overlap", action="store_true",
                     help="frame: bin frame f while frame f - 1 is drawn (mm_set_frame_overlap)")
     ap.add_argument("--hostcopy-frames", type=int, default=10, help="hostcopy: frames timed")
-    ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy", "grid"],
+    ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy", "grid", "edges"],
                     default="frame",
                     help="frame: the 2^24-point 1080p frame (default); batched: 64 clouds "
                          "with 1-4 views each in one launch per pass; served: Poisson "
@@ -554,6 +606,9 @@ def main() -> int:
         return 0
     if args.workload == "served":
         print(json.dumps(bench_served(args)), flush=True)
+        return 0
+    if args.workload == "edges":
+        print(json.dumps(bench_edges(args)), flush=True)
         return 0
     if args.workload == "grid":
         print(json.dumps(bench_grid(args)), flush=True)

@@ -43,6 +43,7 @@ typedef struct mm_view_s* mm_view;
 typedef struct mm_batch_s* mm_batch;
 typedef struct mm_server_s* mm_server;
 typedef struct mm_grid_s* mm_grid;
+typedef struct mm_edges_s* mm_edges;
 
 typedef int32_t mm_status;
 #define MM_OK 0
@@ -301,6 +302,44 @@ mm_status mm_grid_render(mm_grid grid);
 mm_status mm_grid_frame_device_ptr(mm_grid grid, const uint32_t** dev_rgba);
 /* Copies the frame to host memory (bytes >= width * height * 4); synchronises. */
 mm_status mm_grid_read_frame(mm_grid grid, void* host_rgba, size_t bytes);
+
+/* ------------------------------------------------------------------ edges
+ * The paper's edge views (triangle meshes, the Delaunay edges of its colloid
+ * sample): segments between indexed vertices of a point cloud, depth-tested
+ * with the same (depth bits << 32 | id) minimum as points and resolved with
+ * the hash colour of the winning edge id. Segment e from vertex a to b: both
+ * must pass the near test of the point projection; with (dx, dy, dw) the
+ * screen and clip-w differences b - a, it takes n = ceil(max(|dx|, |dy|))
+ * steps (at most 32768) and samples t = k / n, k = 0..n (t = 0 alone when
+ * n = 0): x = ax + t dx, y = ay + t dy, w = aw + t dw in binary32, each
+ * rounded as written; every sample on the screen keys its pixel like a point
+ * (2D: depth bits 0). Edge ids: pair e, or side j of triangle t as 3t + j
+ * (joining its vertices j and (j + 1) mod 3). A vertex index past the vertex
+ * count skips the segment. */
+typedef struct {
+    mm_alloc position;               /* vertices, AoS, as a view's positions */
+    uint64_t element_count;          /* vertices, 1 .. 2^32 - 1 */
+    mm_format format;
+    mm_domain domain;
+    mm_alloc indices;                /* uint32 vertex indices, primitive_count * vpp */
+    uint64_t primitive_count;        /* pairs or triangles (edge ids must fit 32 bits) */
+    uint32_t vertices_per_primitive; /* 2: vertex pairs, 3: triangles */
+    uint32_t width, height;          /* screen, each even and in [2, 16384] */
+    uint64_t seed;                   /* key of the colour hash */
+    float view_proj[16];             /* row-major float32 clip-from-world; 3D only */
+} mm_edges_desc;
+
+/* Creates an edges view with its own key buffer and RGBA8 frame; it keeps
+ * both allocations in use until destroyed. */
+mm_status mm_create_edges(mm_instance inst, const mm_edges_desc* desc, mm_edges* out);
+mm_status mm_destroy_edges(mm_edges view);
+mm_status mm_edges_set_camera(mm_edges view, const float view_proj[16]);
+/* Draws the segments of the current vertex positions and indices (two
+ * kernels on the instance stream: segments, then resolve). */
+mm_status mm_edges_render(mm_edges view);
+mm_status mm_edges_frame_device_ptr(mm_edges view, const uint32_t** dev_rgba);
+/* Copies the frame to host memory (bytes >= width * height * 4); synchronises. */
+mm_status mm_edges_read_frame(mm_edges view, void* host_rgba, size_t bytes);
 
 /* ----------------------------------------------------------------- batches
  * Many point clouds, each drawn into one or more views, rendered together

@@ -62,6 +62,11 @@ def lib() -> C.CDLL:
         L.oracle_step_render.argtypes = [f32p, C.c_uint64, C.c_uint32, C.c_uint64,
                                          C.c_uint32, C.c_float, C.c_int, f32p,
                                          C.c_uint32, C.c_uint32, C.c_uint32, u64p, u32p]
+        L.oracle_screen.argtypes = [f32p, C.c_uint32, f32p, C.c_uint32, C.c_uint32,
+                                    f32p, f32p, f32p]
+        L.oracle_screen.restype = C.c_int
+        L.oracle_splat_edges.argtypes = [f32p, C.c_uint64, C.c_uint32, u32p, C.c_uint64,
+                                         C.c_uint32, f32p, C.c_uint32, C.c_uint32, u64p]
         _lib = L
     return _lib
 
@@ -216,3 +221,29 @@ def render_grid(cols: int, rows: int, width: int, height: int, palette: np.ndarr
     v = cells[cy[:, None] * cols + cx[None, :]]
     inside = v < palette.shape[0]
     return np.where(inside, palette[np.where(inside, v, 0)], 0).astype(np.uint32)
+
+
+def screen(p, m, width: int, height: int):
+    """(sx, sy, w) of a vertex before the pixel floor, or None when near-culled."""
+    p = np.ascontiguousarray(np.asarray(p, dtype=np.float32).reshape(-1))
+    m = _mat(m)
+    sx, sy, w = C.c_float(), C.c_float(), C.c_float()
+    ok = lib().oracle_screen(_ptr(p, C.c_float), p.shape[0], _ptr(m, C.c_float), width, height,
+                             C.byref(sx), C.byref(sy), C.byref(w))
+    return (sx.value, sy.value, w.value) if ok else None
+
+
+def render_edges(pos: np.ndarray, idx: np.ndarray, prim: int, seed: int, m, width: int,
+                 height: int, depth: np.ndarray | None = None) -> np.ndarray:
+    """Edges view frame: segments between indexed vertices (pairs, prim 2, or
+    triangle sides, prim 3) sampled as oracle_splat_edge defines, resolved
+    with the hash colour of the winning edge index."""
+    assert pos.dtype == np.float32 and pos.ndim == 2
+    idx = np.ascontiguousarray(idx, dtype=np.uint32).reshape(-1)
+    assert idx.shape[0] % prim == 0
+    if depth is None:
+        depth = new_depth(width, height)
+    lib().oracle_splat_edges(_ptr(pos, C.c_float), pos.shape[0], pos.shape[1],
+                             _ptr(idx, C.c_uint32), idx.shape[0] // prim, prim, _ptr(_mat(m), C.c_float),
+                             width, height, _ptr(depth, C.c_uint64))
+    return resolve(depth, seed).reshape(height, width)

@@ -228,3 +228,107 @@ void oracle_step_render(float* pos, uint64_t n, uint32_t dim, uint64_t seed,
     oracle_splat(pos, n, dim, m, width, height, footprint, depth, NULL);
     oracle_resolve(depth, colour, (uint64_t)width * height, seed);
 }
+
+
+/* Screen position (before the pixel floor) and clip w of a vertex, as the
+ * point projection computes them: 2D (x + 1) W/2, (y + 1) H/2 and w = 0; 3D
+ * rows 0, 1 and 3 of the camera, each summed left to right, and the same
+ * perspective divide. Returns 0 when the near test (w > 0.1) culls it; the
+ * screen test is left to each sample of a segment. */
+int oracle_screen(const float* p, uint32_t dim, const float m[16], uint32_t width,
+                  uint32_t height, float* sx, float* sy, float* w)
+{
+    const float half_w = (float)(width / 2u);
+    const float half_h = (float)(height / 2u);
+    if (dim == 2u) {
+        *sx = (p[0] + 1.0f) * half_w;
+        *sy = (p[1] + 1.0f) * half_h;
+        *w = 0.0f;
+        return 1;
+    }
+    const float x = p[0], y = p[1], z = p[2];
+    float cx = m[0] * x;
+    cx = cx + m[1] * y;
+    cx = cx + m[2] * z;
+    cx = cx + m[3];
+    float cy = m[4] * x;
+    cy = cy + m[5] * y;
+    cy = cy + m[6] * z;
+    cy = cy + m[7];
+    float cw = m[12] * x;
+    cw = cw + m[13] * y;
+    cw = cw + m[14] * z;
+    cw = cw + m[15];
+    if (!(cw > 0.1f))
+        return 0;
+    const float inv_w = 1.0f / cw;
+    *sx = (cx * inv_w + 1.0f) * half_w;
+    *sy = (cy * inv_w + 1.0f) * half_h;
+    *w = cw;
+    return 1;
+}
+
+/* Reading of the edges view (the paper draws segments between indexed
+ * positions through the raster pipeline): segment e joins vertices a and b.
+ * Both must pass the near test. With dx, dy, dw the screen and depth
+ * differences b - a, the segment takes n = ceil(max(|dx|, |dy|)) steps
+ * (at most EDGE_MAX_STEPS; none for a point-like segment) and samples
+ * t = k / n for k = 0..n: x = ax + t dx, y = ay + t dy, w = aw + t dw, each
+ * rounded as written. Each sample on the screen takes the minimum of its
+ * pixel's key (bits(w) << 32 | e), as a point does. A vertex index past the
+ * vertex count skips the segment. */
+#define EDGE_MAX_STEPS 32768u
+
+void oracle_splat_edge(const float* pos, uint64_t n, uint32_t dim, const float m[16],
+                       uint32_t width, uint32_t height, uint32_t a, uint32_t b, uint32_t e,
+                       uint64_t* depth)
+{
+    if ((uint64_t)a >= n || (uint64_t)b >= n)
+        return;
+    float ax, ay, aw, bx, by, bw;
+    if (!oracle_screen(pos + (uint64_t)a * dim, dim, m, width, height, &ax, &ay, &aw))
+        return;
+    if (!oracle_screen(pos + (uint64_t)b * dim, dim, m, width, height, &bx, &by, &bw))
+        return;
+    const float dx = bx - ax, dy = by - ay, dw = bw - aw;
+    const float len = fmaxf(fabsf(dx), fabsf(dy));
+    const uint32_t steps = len >= (float)EDGE_MAX_STEPS ? EDGE_MAX_STEPS : (uint32_t)ceilf(len);
+    for (uint32_t k = 0; k <= steps; ++k) {
+        const float t = steps == 0u ? 0.0f : (float)k / (float)steps;
+        const float x = ax + t * dx;
+        const float y = ay + t * dy;
+        const float w = aw + t * dw;
+        if (!(x >= 0.0f && x < (float)width && y >= 0.0f && y < (float)height))
+            continue;
+        const int32_t px = (int32_t)floorf(x);
+        const int32_t py = (int32_t)height - 1 - (int32_t)floorf(y);
+        union {
+            float f;
+            uint32_t u;
+        } pun;
+        pun.f = w;
+        const uint64_t key = ((uint64_t)(dim == 2u ? 0u : pun.u) << 32) | (uint64_t)e;
+        uint64_t* slot = depth + (uint64_t)py * width + (uint64_t)px;
+        if (key < *slot)
+            *slot = key;
+    }
+}
+
+/* All segments: pairs (prim == 2: edge e is (idx[2e], idx[2e+1])) or
+ * triangles (prim == 3: triangle t gives edges 3t + j joining idx[3t + j]
+ * and idx[3t + (j + 1) % 3]). */
+void oracle_splat_edges(const float* pos, uint64_t n, uint32_t dim, const uint32_t* idx,
+                        uint64_t nprim, uint32_t prim, const float m[16], uint32_t width,
+                        uint32_t height, uint64_t* depth)
+{
+    for (uint64_t q = 0; q < nprim; ++q) {
+        if (prim == 2u) {
+            oracle_splat_edge(pos, n, dim, m, width, height, idx[2 * q], idx[2 * q + 1],
+                              (uint32_t)q, depth);
+        } else {
+            for (uint32_t j = 0; j < 3u; ++j)
+                oracle_splat_edge(pos, n, dim, m, width, height, idx[3 * q + j],
+                                  idx[3 * q + (j + 1u) % 3u], (uint32_t)(3 * q + j), depth);
+        }
+    }
+}

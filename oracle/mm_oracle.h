@@ -72,6 +72,14 @@ uint32_t oracle_colour(uint32_t index, uint64_t seed);
 /* Resolve and clear: colour[p] = 0 for an empty pixel, else
  * oracle_colour(lo32(depth[p]), seed); then depth[p] = all ones. */
 void oracle_resolve(uint64_t* depth, uint32_t* colour, uint64_t npix, uint64_t seed);
+int oracle_screen(const float* p, uint32_t dim, const float m[16], uint32_t width,
+                  uint32_t height, float* sx, float* sy, float* w);
+void oracle_splat_edge(const float* pos, uint64_t n, uint32_t dim, const float m[16],
+                       uint32_t width, uint32_t height, uint32_t a, uint32_t b, uint32_t e,
+                       uint64_t* depth);
+void oracle_splat_edges(const float* pos, uint64_t n, uint32_t dim, const uint32_t* idx,
+                        uint64_t nprim, uint32_t prim, const float m[16], uint32_t width,
+                        uint32_t height, uint64_t* depth);
 
 /* One whole frame: displace with step s, splat, resolve. depth must hold
  * all-ones keys on entry and holds them again on return. */

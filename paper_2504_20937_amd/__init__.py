@@ -90,6 +90,22 @@ class mm_grid_desc(C.Structure):
     ]
 
 
+class mm_edges_desc(C.Structure):
+    _fields_ = [
+        ("position", C.c_void_p),
+        ("element_count", C.c_uint64),
+        ("format", C.c_int),
+        ("domain", C.c_int),
+        ("indices", C.c_void_p),
+        ("primitive_count", C.c_uint64),
+        ("vertices_per_primitive", C.c_uint32),
+        ("width", C.c_uint32),
+        ("height", C.c_uint32),
+        ("seed", C.c_uint64),
+        ("view_proj", C.c_float * 16),
+    ]
+
+
 class mm_cloud_desc(C.Structure):
     _fields_ = [
         ("position", C.c_void_p),
@@ -168,6 +184,12 @@ def _declare(L):
         "mm_set_frame_overlap": ([_vp, C.c_uint32], _status),
         "mm_set_colour": ([_vp, C.POINTER(mm_colour_desc)], _status),
         "mm_create_grid": ([_vp, C.POINTER(mm_grid_desc), C.POINTER(_vp)], _status),
+        "mm_create_edges": ([_vp, C.POINTER(mm_edges_desc), C.POINTER(_vp)], _status),
+        "mm_destroy_edges": ([_vp], _status),
+        "mm_edges_set_camera": ([_vp, C.POINTER(C.c_float)], _status),
+        "mm_edges_render": ([_vp], _status),
+        "mm_edges_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
+        "mm_edges_read_frame": ([_vp, _vp, C.c_size_t], _status),
         "mm_destroy_grid": ([_vp], _status),
         "mm_grid_render": ([_vp], _status),
         "mm_grid_frame_device_ptr": ([_vp, C.POINTER(_vp)], _status),
@@ -391,6 +413,45 @@ def mm_grid_frame_device_ptr(grid: int) -> int:
 def mm_grid_read_frame(grid: int, width: int, height: int) -> np.ndarray:
     out = np.empty((height, width), dtype=np.uint32)
     _check(lib().mm_grid_read_frame(grid, out.ctypes.data, out.nbytes), "mm_grid_read_frame")
+    return out
+
+
+def mm_create_edges(inst: int, position, n: int, dim: int, indices, nprim: int, prim: int,
+                    width: int, height: int, seed: int, view_proj=None) -> int:
+    """Edges view over n vertices (position, an mm_alloc) joined by nprim
+    vertex pairs (prim 2) or triangles (prim 3) of uint32 indices (an mm_alloc)."""
+    m = np.eye(4, dtype=np.float32).reshape(16) if view_proj is None else \
+        np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(16))
+    d = mm_edges_desc(position, n, dim, dim, indices, nprim, prim, width, height, seed,
+                      (C.c_float * 16)(*m.tolist()))
+    out = _vp()
+    _check(lib().mm_create_edges(inst, C.byref(d), C.byref(out)), "mm_create_edges")
+    return out.value
+
+
+def mm_destroy_edges(view: int) -> None:
+    _check(lib().mm_destroy_edges(view), "mm_destroy_edges")
+
+
+def mm_edges_set_camera(view: int, view_proj) -> None:
+    m = np.ascontiguousarray(np.asarray(view_proj, dtype=np.float32).reshape(16))
+    _check(lib().mm_edges_set_camera(view, m.ctypes.data_as(C.POINTER(C.c_float))),
+           "mm_edges_set_camera")
+
+
+def mm_edges_render(view: int) -> None:
+    _check(lib().mm_edges_render(view), "mm_edges_render")
+
+
+def mm_edges_frame_device_ptr(view: int) -> int:
+    out = _vp()
+    _check(lib().mm_edges_frame_device_ptr(view, C.byref(out)), "mm_edges_frame_device_ptr")
+    return out.value
+
+
+def mm_edges_read_frame(view: int, width: int, height: int) -> np.ndarray:
+    out = np.empty((height, width), dtype=np.uint32)
+    _check(lib().mm_edges_read_frame(view, out.ctypes.data, out.nbytes), "mm_edges_read_frame")
     return out
 
 

@@ -1,9 +1,9 @@
 // Structured-grid view: a cols x rows lattice of cells, each drawn as the
 // palette entry of its cell value, filling the screen (the paper's voxel view
 // of a 2D structured domain, as used for the Potts-model lattice, with colour
-// from a colormap through the cell's index). One thread per pixel: the cell
-// under the pixel centre by integer arithmetic, one index load, one palette
-// load, one non-temporal colour store.
+// from a colormap through the cell's index). Each thread takes four pixels of
+// a row: the cell under each pixel centre by integer arithmetic, an index
+// load, a palette load and a non-temporal colour store per pixel.
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -21,22 +21,40 @@ struct GridArgs {
 };
 
 // Cell column of pixel column px: floor((px + 1/2) * cols / width), exactly.
+// (2 px + 1) * cells < 32769 * 65536 < 2^32, so 32-bit arithmetic is exact.
 __device__ __forceinline__ uint32_t cell_of(uint32_t p, uint32_t cells, uint32_t pixels) {
-    return static_cast<uint32_t>((2ull * p + 1ull) * cells / (2ull * pixels));
+    return (2u * p + 1u) * cells / (2u * pixels);
+}
+
+// Four pixels per thread, 256 apart, so their loads are in flight together.
+constexpr uint32_t kGridPix = 4;
+
+__device__ __forceinline__ uint32_t cell_value(const GridArgs& a, uint64_t cell) {
+    if (a.index_size == 1) return static_cast<const uint8_t*>(a.index)[cell];
+    if (a.index_size == 2) return static_cast<const uint16_t*>(a.index)[cell];
+    return static_cast<const uint32_t*>(a.index)[cell];
 }
 
 __global__ __launch_bounds__(256) void grid_kernel(GridArgs a) {
-    const uint32_t px = blockIdx.x * 256u + threadIdx.x, py = blockIdx.y;
-    if (px >= a.width) return;
-    const uint32_t cx = cell_of(px, a.cols, a.width);
-    const uint32_t cy = cell_of(a.height - 1u - py, a.rows, a.height);  // y up
-    const uint64_t cell = static_cast<uint64_t>(cy) * a.cols + cx;
-    uint32_t j;
-    if (a.index_size == 1) j = static_cast<const uint8_t*>(a.index)[cell];
-    else if (a.index_size == 2) j = static_cast<const uint16_t*>(a.index)[cell];
-    else j = static_cast<const uint32_t*>(a.index)[cell];
-    const uint32_t c = j < a.palette_size ? a.palette[j] : 0u;
-    __builtin_nontemporal_store(c, a.colour + static_cast<uint64_t>(py) * a.width + px);
+    const uint32_t py = blockIdx.y;
+    const uint32_t cy = cell_of(a.height - 1u - py, a.rows, a.height);  // y up; uniform per block
+    const uint64_t row = static_cast<uint64_t>(cy) * a.cols;
+    const uint32_t x0 = blockIdx.x * (256u * kGridPix) + threadIdx.x;
+    uint32_t v[kGridPix];
+#pragma unroll
+    for (uint32_t k = 0; k < kGridPix; ++k) {
+        const uint32_t px = min(x0 + k * 256u, a.width - 1u);  // tail lanes repeat the last pixel
+        v[k] = cell_value(a, row + cell_of(px, a.cols, a.width));
+    }
+    uint32_t c[kGridPix];
+#pragma unroll
+    for (uint32_t k = 0; k < kGridPix; ++k) c[k] = v[k] < a.palette_size ? a.palette[v[k]] : 0u;
+    uint32_t* out = a.colour + static_cast<uint64_t>(py) * a.width;
+#pragma unroll
+    for (uint32_t k = 0; k < kGridPix; ++k) {
+        const uint32_t px = x0 + k * 256u;
+        if (px < a.width) __builtin_nontemporal_store(c[k], out + px);
+    }
 }
 
 }  // namespace
@@ -110,7 +128,7 @@ mm_status mm_destroy_grid(mm_grid g) {
 mm_status mm_grid_render(mm_grid g) {
     if (!g) return fail(MM_ERR_INVALID_ARG, "grid_render: null grid");
     DeviceGuard guard(g->inst->device);
-    const dim3 grid((g->args.width + 255u) / 256u, g->args.height);
+    const dim3 grid((g->args.width + 256u * kGridPix - 1u) / (256u * kGridPix), g->args.height);
     GridArgs a = g->args;
     void* args[] = {&a};
     MM_HIP(hipLaunchKernel(reinterpret_cast<const void*>(&grid_kernel), grid, dim3(256), args, 0,

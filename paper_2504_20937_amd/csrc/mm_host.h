@@ -32,6 +32,7 @@ struct mm_instance_s {
     std::set<mm_batch> batches;
     std::set<mm_server> servers;
     std::set<mm_grid> grids;
+    std::set<mm_edges> edges;
 };
 
 namespace mmh {

@@ -585,7 +585,7 @@ mm_status mm_create_instance(const mm_instance_desc* desc, mm_instance* out) {
         MM_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         owns = true;
     }
-    mm_instance inst = new (std::nothrow) mm_instance_s{desc->device, s, owns, {}, {}, {}, {}, {}};
+    mm_instance inst = new (std::nothrow) mm_instance_s{desc->device, s, owns, {}, {}, {}, {}, {}, {}};
     if (!inst) {
         if (owns) (void)hipStreamDestroy(s);
         return fail(MM_ERR_OUT_OF_MEMORY, "create_instance: host allocation");
@@ -611,6 +611,8 @@ mm_status mm_destroy_instance(mm_instance inst) {
     for (mm_server v : servers) mm_destroy_server(v);
     std::vector<mm_grid> grids(inst->grids.begin(), inst->grids.end());
     for (mm_grid g : grids) mm_destroy_grid(g);
+    std::vector<mm_edges> edge_views(inst->edges.begin(), inst->edges.end());
+    for (mm_edges g : edge_views) mm_destroy_edges(g);
     std::vector<mm_batch> batches(inst->batches.begin(), inst->batches.end());
     for (mm_batch b : batches) mm_destroy_batch(b);
     std::vector<mm_view> views(inst->views.begin(), inst->views.end());

@@ -64,6 +64,10 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.mm_destroy_grid(None) == mm.MM_ERR_INVALID_ARG
     assert L.mm_grid_render(None) == mm.MM_ERR_INVALID_ARG
     assert L.mm_grid_read_frame(None, None, 0) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_create_edges(None, None, None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_destroy_edges(None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_edges_render(None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_edges_set_camera(None, None) == mm.MM_ERR_INVALID_ARG
 
 
 def test_view_desc_layout_matches_header():
@@ -129,6 +133,7 @@ def test_batch_struct_layouts_match_the_header(tmp_path):
         "mm_batch_tuning": mm.mm_batch_tuning,
         "mm_colour_desc": mm.mm_colour_desc,
         "mm_grid_desc": mm.mm_grid_desc,
+        "mm_edges_desc": mm.mm_edges_desc,
     }
     exprs, expect = [], []
     for cname, py in structs.items():
