@@ -139,6 +139,16 @@ def test_3d_mixture_4k_footprint3(rig, mode):
          lambda s: synth.orbit_camera(s, 3840, 2160), mode=mode)
 
 
+def test_3d_mixture_2p28_4k_footprint3_full_size(rig):
+    """The 4K benchmark at its full size, in the launch configuration the
+    benchmark times (default tuning: 64-pixel tiles, the tile pass balanced
+    by load): one frame and every position."""
+    say("case: 3D mixture, 2^28 points, 3840x2160, 3x3 footprint, 1 frame (full benchmark size)")
+    pts = synth.gaussian_mixture(1 << 28, seed=0)
+    _run(rig, pts, 3, 3840, 2160, 3, 0, 0.001, False, 1,
+         lambda s: synth.orbit_camera(s, 3840, 2160))
+
+
 @pytest.mark.parametrize("mode", SHAPES, ids=_ids(SHAPES))
 @pytest.mark.parametrize("n", [1, 2, 255, 256, 257, 511, 1025, 4097])
 def test_tiny_and_ragged_counts(rig, n, mode):
