@@ -660,10 +660,16 @@ def main() -> int:
     mm.mm_profile_begin(view, prof_cap)  # synchronises
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # the loop calls the C entry points directly with cameras converted
+    # beforehand, so Python adds as little as possible to the host side of a
+    # frame (each call's status is still checked)
+    L = mm.lib()
+    cam_arrs = [np.ascontiguousarray(cams[W + k], dtype=np.float32).reshape(16) for k in range(K)]
+    cam_ptrs = [mm._fptr(a) for a in cam_arrs]  # cam_arrs keeps the memory alive
     for k in range(K):
-        f = W + k
-        mm.mm_set_camera(view, cams[f])
-        mm.mm_step_render(view, f)
+        st = L.mm_set_camera(view, cam_ptrs[k]) or L.mm_step_render(view, W + k)
+        if st:
+            raise mm.MMError(st, "frame loop", mm.mm_last_error())
     mm.mm_flush_frame(view)  # with overlap, the last frame is drawn inside the timed region
     torch.cuda.synchronize()
     t1 = time.perf_counter()

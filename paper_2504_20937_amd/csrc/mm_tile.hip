@@ -3,10 +3,13 @@
 // footprints, each as a plain kernel (one view, kernel arguments) and a
 // batched kernel (items (view, tile) from a device table).
 //
-// tile kernel (one workgroup per screen tile and split): pull the tile's
-//   column of the table into LDS, read the chunks coalesced (a group of lanes
-//   per chunk, many chunks in flight), take the min (depth_bits << 32 |
-//   index) per pixel with LDS atomics, and write the partial keys of the tile.
+// tile kernel (one workgroup per screen tile and split, or per piece of a
+//   tile with the load-balanced pass): gather the tile's (start, end) pairs
+//   from the table, compact the non-empty runs with a block scan, walk the
+//   tile's records as one flat list (64 consecutive records per wave step,
+//   runs found through an LDS bitmap of run starts), take the min
+//   (depth_bits << 32 | index) per centre pixel with LDS atomics, and write
+//   the tile's partial keys (a 3x3 footprint as a 3x3 minimum over them).
 // merge kernel (one workgroup per tile): min over the splits, resolve to
 //   RGBA8 directly: no full-screen key buffer, no clear pass. With the 3x3
 //   footprint the tile carries a one-pixel apron; edge pixels and the apron
