@@ -279,6 +279,41 @@ def test_profile_records_kernel_times(rig, mode):
     assert same_bits(rig.positions(dev), ref)
 
 
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_profile_sampling_records_one_frame_in_every(rig, mode):
+    say("case: mm_profile_every 3, capacity 4, 14 frames, 2^18 points 640x480")
+    mm = rig.mm
+    pts = synth.uniform_cube(1 << 18, seed=5)
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, 1 << 18, 3, 640, 480, 1, 7, 0.002, True,
+                    synth.orbit_camera(0, 640, 480))
+    mm.mm_set_tuning(view, *mode)
+    with pytest.raises(RuntimeError):
+        mm.mm_profile_every(view, 0)
+    with pytest.raises(RuntimeError):
+        mm.mm_profile_every(view, 1001)
+    mm.mm_profile_every(view, 3)
+    mm.mm_profile_begin(view, 4)
+    ref = pts.copy()
+    for s in range(14):  # frames 0, 3, 6, 9 are recorded; 12 finds the buffer full
+        mm.mm_set_camera(view, synth.orbit_camera(s, 640, 480))
+        mm.mm_step_render(view, s)
+        want = oracle.step_render(ref, 7, s, 0.002, True, synth.orbit_camera(s, 640, 480),
+                                  640, 480, 1)
+        if s in (2, 3, 13):  # a plain frame, a timed frame, a frame past capacity
+            assert np.array_equal(mm.mm_read_frame(view, 640, 480), want), s
+    sp, rs, fr = mm.mm_profile_end(view, 4)
+    assert sp.shape == (4,) and np.all(sp > 0) and np.all(rs > 0) and np.all(fr >= sp)
+    assert same_bits(rig.positions(dev), ref)
+    # back to every frame: a new profile of 3 frames records 3
+    mm.mm_profile_every(view, 1)
+    mm.mm_profile_begin(view, 3)
+    for s in range(14, 17):
+        mm.mm_step_render(view, s)
+    sp, _, _ = mm.mm_profile_end(view, 3)
+    assert sp.shape == (3,)
+
+
 def test_invalid_descriptions_are_rejected(rig):
     say("case: invalid view descriptions and wraps")
     mm = rig.mm
