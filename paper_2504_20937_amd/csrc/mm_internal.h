@@ -81,6 +81,10 @@ struct TileView {
     uint32_t splits;     // tile-pass workgroups per tile (static splits)
     const uint32_t* piece_first;  // load-balanced: ntiles + 1 first partial block of
                                   // each tile (nullptr: static splits)
+    const uint16_t* tcol;         // load-balanced: the table tile-major, row t (of
+                                  // ntiles + 1, tcol_stride entries each) holding
+                                  // entry t of every table row (nullptr: read the rows)
+    uint32_t tcol_stride;
     uint32_t full_clear; // 1: clear every tile not drawn this frame (the frame buffer
                          // holds no earlier frame); 0: only tiles drawn last frame
     uint32_t seed_lo, seed_hi;
@@ -101,7 +105,8 @@ struct TileArgs {
     const uint32_t* stamp_in;
     uint32_t points_per_wg;
     // load-balanced tile pass
-    uint32_t* tile_total;    // ntiles record counts (zero between frames)
+    uint32_t* col_sum;       // ntiles + 1 column sums of the table (zero between frames)
+    uint16_t* tcol;          // written by the transpose pass (the same array as v.tcol)
     uint32_t* piece_first;   // ntiles + 1 (the same array as v.piece_first)
     uint2* items;            // work items: (tile, piece << 16 | pieces of the tile)
     uint32_t* counters;      // [0] next item, [1] items this frame
@@ -167,9 +172,11 @@ Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t threads, ui
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits);
 Launch merge_launch(int footprint, int shift, uint32_t ntiles);
 Launch seam_launch(int shift, uint32_t ntiles);
-// Load-balanced tile pass: count, plan, then a persistent grid of tile
-// workgroups over the work list.
-Launch count_launch(uint32_t ntiles, uint32_t num_wg);
+// Load-balanced tile pass: the table made tile-major with the tiles' record
+// totals, the plan, then a persistent grid of tile workgroups over the work
+// list. The tile-major rows hold tcol_stride(num_wg) entries.
+uint32_t tcol_stride(uint32_t num_wg);
+Launch transpose_launch(uint32_t ntiles, uint32_t num_wg);
 Launch plan_launch();
 Launch tile_list_launch(int footprint, int shift, uint32_t grid_blocks);
 

@@ -52,7 +52,8 @@ struct mm_view_s {
     uint64_t* border = nullptr;
     uint64_t* apron = nullptr;
     // load-balanced tile pass
-    uint32_t* tile_total = nullptr;
+    uint32_t* col_sum = nullptr;
+    uint16_t* tcol = nullptr;
     uint32_t* piece_first = nullptr;
     uint2* items = nullptr;
     uint32_t* counters = nullptr;
@@ -149,7 +150,8 @@ void free_splat_buffers(mm_view v) {
     for (void* p : {static_cast<void*>(v->depth), static_cast<void*>(v->seg),
                     static_cast<void*>(v->table), static_cast<void*>(v->active),
                     static_cast<void*>(v->part), static_cast<void*>(v->border),
-                    static_cast<void*>(v->apron), static_cast<void*>(v->tile_total),
+                    static_cast<void*>(v->apron), static_cast<void*>(v->col_sum),
+                    static_cast<void*>(v->tcol),
                     static_cast<void*>(v->piece_first), static_cast<void*>(v->items),
                     static_cast<void*>(v->counters)})
         if (p) (void)hipFree(p);
@@ -159,7 +161,8 @@ void free_splat_buffers(mm_view v) {
     v->seg1 = nullptr;
     v->table1 = nullptr;
     v->active1 = nullptr;
-    v->tile_total = nullptr;
+    v->col_sum = nullptr;
+    v->tcol = nullptr;
     v->piece_first = nullptr;
     v->items = nullptr;
     v->counters = nullptr;
@@ -280,8 +283,12 @@ mm_status setup_splat(mm_view v) {
                                          : static_cast<uint64_t>(v->ntiles) * v->tuning.splits;
         if (e == hipSuccess) e = alloc_n(&v->part, blocks * side_a * side_a);
         if (e == hipSuccess && balanced) {
-            e = alloc_n(&v->tile_total, v->ntiles);
-            if (e == hipSuccess) e = hipMemsetAsync(v->tile_total, 0, sizeof(uint32_t) * v->ntiles, inst->stream);
+            e = alloc_n(&v->col_sum, static_cast<uint64_t>(v->ntiles) + 1);
+            if (e == hipSuccess)
+                e = hipMemsetAsync(v->col_sum, 0, sizeof(uint32_t) * (static_cast<size_t>(v->ntiles) + 1),
+                                   inst->stream);
+            if (e == hipSuccess)
+                e = alloc_n(&v->tcol, (static_cast<uint64_t>(v->ntiles) + 1) * mm::tcol_stride(v->num_wg));
             if (e == hipSuccess) e = alloc_n(&v->piece_first, static_cast<uint64_t>(v->ntiles) + 1);
             if (e == hipSuccess) e = alloc_n(&v->items, blocks);
             if (e == hipSuccess) e = alloc_n(&v->counters, 2);
@@ -320,12 +327,15 @@ mm_status setup_splat(mm_view v) {
         t.v.num_wg = v->num_wg;
         t.v.splits = v->tuning.splits;
         t.v.piece_first = v->piece_first;
+        t.v.tcol = v->tcol;
+        t.v.tcol_stride = balanced ? mm::tcol_stride(v->num_wg) : 0u;
         t.v.seed_lo = v->args.c.seed_lo;
         t.v.seed_hi = v->args.c.seed_hi;
         t.v.pal = v->pal;
         t.stamp_in = v->active + v->ntiles;
         t.points_per_wg = static_cast<uint32_t>(P);
-        t.tile_total = v->tile_total;
+        t.col_sum = v->col_sum;
+        t.tcol = v->tcol;
         t.piece_first = v->piece_first;
         t.items = v->items;
         t.counters = v->counters;
@@ -360,7 +370,7 @@ mm_status setup_splat(mm_view v) {
                 cus <= 0)
                 cus = 256;
             const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(blocks, 2ull * cus));
-            v->nodes.push_back(mm::count_launch(v->ntiles, v->num_wg));
+            v->nodes.push_back(mm::transpose_launch(v->ntiles, v->num_wg));
             v->nodes.push_back(mm::plan_launch());
             v->nodes.push_back(mm::tile_list_launch(foot, static_cast<int>(shift), grid));
         } else {

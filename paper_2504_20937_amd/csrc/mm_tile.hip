@@ -5,16 +5,17 @@
 //
 // tile kernel (one workgroup per screen tile and split, or per piece of a
 //   tile with the load-balanced pass): gather the tile's (start, end) pairs
-//   from the table, compact the non-empty runs with a block scan, walk the
+//   from the table (or its tile-major copy, which the load-balanced pass
+//   makes first), compact the non-empty runs with a block scan, walk the
 //   tile's records as one flat list (64 consecutive records per wave step,
 //   runs found through an LDS bitmap of run starts), take the min
 //   (depth_bits << 32 | index) per centre pixel with LDS atomics, and write
 //   the tile's partial keys (a 3x3 footprint as a 3x3 minimum over them).
-// merge kernel (one workgroup per tile): min over the splits, resolve to
-//   RGBA8 directly: no full-screen key buffer, no clear pass. With the 3x3
-//   footprint the tile carries a one-pixel apron; edge pixels and the apron
-//   go to small global arrays, and the seam kernel merges edges across tile
-//   borders.
+// merge kernel (one workgroup per tile, four for 64-pixel tiles): min over
+//   the splits or pieces, resolve to RGBA8 directly: no full-screen key
+//   buffer, no clear pass. With the 3x3 footprint the tile carries a
+//   one-pixel apron; edge pixels and the apron go to small global arrays,
+//   and the seam kernel merges edges across tile borders.
 #include "mm_device.h"
 
 namespace mm {
@@ -226,15 +227,26 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
     for (uint32_t base = w_lo; base < w_hi; base += kCol) {
         const uint32_t nb = min(kCol, w_hi - base);
         __syncthreads();  // keys initialised / previous pass done with the LDS
-        // Branch-free: lanes past the column's end read its last row (count
+        // Branch-free: lanes past the column's end read its last entry (count
         // forced to 0), so all of a lane's table loads are in flight together.
         uint32_t cs[kPer], cn[kPer];
+        if (v.tcol) {  // tile-major copy: entries t and t + 1 of each row, contiguous
+            const uint16_t* e0 = v.tcol + static_cast<uint64_t>(t) * v.tcol_stride + base;
+            const uint16_t* e1 = e0 + v.tcol_stride;
 #pragma unroll
-        for (uint32_t k = 0; k < kPer; ++k) {
-            const uint32_t c = tid * kPer + k;
-            const uint16_t* row = v.table + static_cast<uint64_t>(base + min(c, nb - 1u)) * stride;
-            cs[k] = row[t];
-            cn[k] = row[t + 1];
+            for (uint32_t k = 0; k < kPer; ++k) {
+                const uint32_t c = min(tid * kPer + k, nb - 1u);
+                cs[k] = e0[c];
+                cn[k] = e1[c];
+            }
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < kPer; ++k) {
+                const uint32_t c = tid * kPer + k;
+                const uint16_t* row = v.table + static_cast<uint64_t>(base + min(c, nb - 1u)) * stride;
+                cs[k] = row[t];
+                cn[k] = row[t + 1];
+            }
         }
         uint32_t tc = 0, tr = 0;  // this thread's records and non-empty runs
 #pragma unroll
@@ -318,56 +330,100 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a) {
     tile_split<FOOT, SHIFT>(a.v, t, z, a.points_per_wg, keys, col);
 }
 
-// Load-balanced tile pass. Per tile, the count kernel sums the records over
-// all bin workgroups; the plan kernel cuts every tile into pieces of about
-// piece_records records (ranges of bin workgroups of equal length), lays the
-// pieces out tile by tile (piece_first) and lists them as work items; a
-// persistent grid of tile workgroups takes items from a counter, so dense
-// tiles spread over many CUs and no workgroup is launched for an empty tile.
+// Load-balanced tile pass. The transpose kernel copies the table tile-major
+// and sums every tile's records over all bin workgroups; the plan kernel cuts
+// every tile into pieces of about piece_records records (ranges of bin
+// workgroups of equal length), lays the pieces out tile by tile (piece_first)
+// and lists them as work items; a persistent grid of tile workgroups takes
+// items from a counter, so dense tiles spread over many CUs and no workgroup
+// is launched for an empty tile. With the tile-major copy a piece reads its
+// tile's entries as two contiguous runs instead of one 128-byte line per bin
+// workgroup: the column gather of a row-major table fetches lines that the
+// 64 tiles sharing them read at different times, long after L2 has let them go.
 
-// Grid (ceil(ntiles / 64), row groups), 64 threads: thread t sums its tile's
-// counts over a range of table rows (64 consecutive tiles read one 128-byte
-// line of each row), then adds them to the tile's total.
-__global__ __launch_bounds__(64) void count_kernel(TileArgs a) {
-    const uint32_t t = blockIdx.x * 64u + threadIdx.x;
-    if (t >= a.v.ntiles) return;
-    const uint32_t rows = (a.v.num_wg + gridDim.y - 1) / gridDim.y;
-    const uint32_t r0 = blockIdx.y * rows, r1 = min(a.v.num_wg, r0 + rows);
-    const uint32_t stride = a.v.ntiles + 1u;
-    uint32_t sum = 0;
-    uint32_t r = r0;
-    for (; r + 8 <= r1; r += 8) {
-        uint32_t s0[8], s1[8];
+// Tile-major rows are whole 128-byte lines apart.
+constexpr uint32_t kTcolAlign = 64;
+// Table rows (bin workgroups) per transpose workgroup, and rows of loads each
+// wave keeps in flight.
+constexpr uint32_t kTransRows = 256;
+constexpr uint32_t kTransBatch = 32;
+
+// One workgroup per (column group, row group), 256 threads. A table row is
+// ntiles + 1 entries long, so a 64-column span mostly straddles two lines
+// that the neighbouring column groups share: block b runs on XCD b mod 8, and
+// blocks b, b + 8, b + 16, ... take column groups 0, 1, 2, ... of one row
+// group, reading the shared lines into one L2 at about the same time. The
+// workgroup stages table columns [t0, t0 + 64) of rows [c0, c0 + kTransRows)
+// in LDS (each row read as one 128-byte span), writes tile-major rows t0 ..
+// t0 + 63 of those entries (a thread 4 consecutive entries), and adds each
+// column's sum over its rows to col_sum. Tile t's records over all bin
+// workgroups are col_sum[t + 1] - col_sum[t] (the table rows are exclusive
+// scans), exact in 32-bit wrap-around arithmetic.
+__global__ __launch_bounds__(256) void transpose_kernel(TileArgs a) {
+    __shared__ uint16_t s[kTransRows][65];
+    __shared__ uint32_t part[4][64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t cols_total = a.v.ntiles + 1u;
+    const uint32_t groups = (cols_total + 63u) / 64u;
+    const uint32_t k = blockIdx.x >> 3;
+    const uint32_t rg = (k / groups) * 8u + (blockIdx.x & 7u);
+    if (rg * kTransRows >= a.v.num_wg) return;
+    const uint32_t t0 = (k % groups) * 64u, c0 = rg * kTransRows;
+    const uint32_t rows = min(kTransRows, a.v.num_wg - c0);
+    const uint32_t cols = min(64u, cols_total - t0);  // columns staged: t0 .. t0 + cols - 1
+    const uint32_t col = min(lane, cols - 1u);
+    // wave w stages rows [32 w, 32 w + 32), [32 w + 128, ...); rows past the
+    // end repeat the last one and count nothing
+    uint32_t acc = 0;
+    for (uint32_t r0 = wave * kTransBatch; r0 < rows; r0 += 4u * kTransBatch) {
+        uint32_t x[kTransBatch];
 #pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) {
-            const uint16_t* row = a.v.table + static_cast<uint64_t>(r + k) * stride;
-            s0[k] = row[t];
-            s1[k] = row[t + 1];
+        for (uint32_t u = 0; u < kTransBatch; ++u)
+            x[u] = a.v.table[static_cast<uint64_t>(c0 + min(r0 + u, rows - 1u)) * cols_total + t0 + col];
+#pragma unroll
+        for (uint32_t u = 0; u < kTransBatch; ++u) {
+            if (r0 + u < rows) {
+                s[r0 + u][lane] = static_cast<uint16_t>(x[u]);
+                acc += x[u];
+            }
         }
-#pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) sum += s1[k] - s0[k];
     }
-    for (; r < r1; ++r) {
-        const uint16_t* row = a.v.table + static_cast<uint64_t>(r) * stride;
-        sum += static_cast<uint32_t>(row[t + 1]) - row[t];
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0u && lane < cols)
+        atomicAdd(&a.col_sum[t0 + lane], part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+    // tile-major rows t0 + j: thread (j mod 4 = wave, lane) writes entries
+    // 4 lane .. 4 lane + 3 of the workgroup's rows
+    const uint32_t stride = a.v.tcol_stride;
+    const uint32_t r = 4u * lane;
+    for (uint32_t j = wave; j < cols; j += 4u) {
+        uint16_t* dst = a.tcol + static_cast<uint64_t>(t0 + j) * stride + c0 + r;
+        if (r + 3u < rows) {
+            const uint64_t w4 = static_cast<uint64_t>(s[r][j]) |
+                                (static_cast<uint64_t>(s[r + 1u][j]) << 16) |
+                                (static_cast<uint64_t>(s[r + 2u][j]) << 32) |
+                                (static_cast<uint64_t>(s[r + 3u][j]) << 48);
+            *reinterpret_cast<uint64_t*>(dst) = w4;
+        } else {
+            for (uint32_t q = 0; r + q < rows; ++q) dst[q] = s[r + q][j];
+        }
     }
-    if (sum) atomicAdd(&a.tile_total[t], sum);
 }
 
 // One workgroup of 1024 threads: pieces per tile, their exclusive scan
 // (piece_first), the work items, the item count; resets the work counter and
-// the tile totals for the next frame.
+// the column sums for the next frame.
 __global__ __launch_bounds__(1024) void plan_kernel(TileArgs a) {
     __shared__ uint32_t pieces[kMaxPlanTiles + 1];
     __shared__ uint32_t wave_sum[16];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
     const uint32_t nt = a.v.ntiles;
     for (uint32_t t = tid; t < nt; t += 1024u) {
-        const uint32_t total = a.tile_total[t];
+        const uint32_t total = a.col_sum[t + 1u] - a.col_sum[t];
         pieces[t] = (total + a.piece_records - 1) / a.piece_records;
-        a.tile_total[t] = 0u;
     }
-    __syncthreads();
+    __syncthreads();  // every sum read before any is reset
+    for (uint32_t t = tid; t <= nt; t += 1024u) a.col_sum[t] = 0u;
     // exclusive scan of pieces[0..nt): each wave a contiguous run of 64-blocks
     const uint32_t nblk = (nt + 63u) / 64u, per = (nblk + 15u) / 16u;
     const uint32_t b0 = min(nblk, wave * per), b1 = min(nblk, b0 + per);
@@ -448,12 +504,14 @@ __global__ __launch_bounds__(kTileThreads) void batch_tile_kernel(BatchTileArgs 
 // Tile t: the minimum of the splits' partial keys, then RGBA8 (edge keys and
 // the apron of 3x3 footprints go to the seam pass). A tile with nothing to
 // draw is cleared if the previous frame drew it; otherwise its pixels are
-// already 0. 256 threads.
+// already 0. 256 threads; workgroup g of G takes pixels (and apron keys) q
+// with q / 256 = g mod G, so a tile of many pieces is merged by several CUs.
 template <int FOOT, int SHIFT>
-__device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32_t stamp) {
+__device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32_t stamp,
+                                           uint32_t g, uint32_t G) {
     constexpr uint32_t S = 1u << SHIFT;
     constexpr uint32_t A = FOOT == 3 ? S + 2 : S;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x + 256u * g, step = 256u * G;
     const uint32_t tx = t % v.tiles_x, ty = t / v.tiles_x;
     const uint32_t x0 = tx << SHIFT, y0 = ty << SHIFT;
     const uint32_t wt = min(S, v.width - x0), ht = min(S, v.height - y0);
@@ -461,7 +519,7 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
     const uint32_t flag = tile_flag(v, t);
     if (flag != stamp) {
         if (flag == stamp - 1u || v.full_clear) {
-            for (uint32_t q = tid; q < S * S; q += 256u) {
+            for (uint32_t q = tid; q < S * S; q += step) {
                 const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
                 if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * v.width + lx] = 0u;
             }
@@ -490,7 +548,7 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
         }
         return k;
     };
-    for (uint32_t q = tid; q < S * S; q += 256u) {
+    for (uint32_t q = tid; q < S * S; q += step) {
         const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
         if (lx >= wt || ly >= ht) continue;
         if constexpr (FOOT == 1) {
@@ -510,7 +568,7 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
     }
     if constexpr (FOOT == 3) {
         uint64_t* ap = v.apron + static_cast<uint64_t>(t) * (4 * S + 4);
-        for (uint32_t q = tid; q < 4 * S + 4; q += 256u) {
+        for (uint32_t q = tid; q < 4 * S + 4; q += step) {
             uint32_t ax, ay;
             ring_coord<S>(q, ax, ay);
             ap[q] = key_at(ay * A + ax);
@@ -522,7 +580,7 @@ template <int FOOT, int SHIFT>
 __global__ __launch_bounds__(256) void merge_kernel(TileArgs a) {
     const uint32_t t = blockIdx.x;
     if (t >= a.v.ntiles) return;
-    merge_tile<FOOT, SHIFT>(a.v, t, *a.stamp_in);
+    merge_tile<FOOT, SHIFT>(a.v, t, *a.stamp_in, blockIdx.y, gridDim.y);
 }
 
 template <int FOOT, int SHIFT>
@@ -532,7 +590,7 @@ __global__ __launch_bounds__(256) void batch_merge_kernel(BatchTileArgs a) {
         const uint2 item = load_uniform(&a.item[it]);
         if (item.x == kPadItem) continue;
         const TileView v = load_uniform(&a.views[item.x]);
-        merge_tile<FOOT, SHIFT>(v, item.y >> 3, stamp);
+        merge_tile<FOOT, SHIFT>(v, item.y >> 3, stamp, 0u, 1u);
     }
 }
 
@@ -675,7 +733,8 @@ Launch merge_launch(int footprint, int shift, uint32_t ntiles) {
     Launch l;
     l.func = footprint == 3 ? pick_merge<3>(shift, false) : pick_merge<1>(shift, false);
     l.block = dim3(256);
-    l.grid = dim3(ntiles);
+    // workgroups per tile: about 1024 pixels each
+    l.grid = dim3(ntiles, shift == 6 ? 4u : 1u);
     l.shared = 0;
     return l;
 }
@@ -689,12 +748,17 @@ Launch seam_launch(int shift, uint32_t ntiles) {
     return l;
 }
 
-Launch count_launch(uint32_t ntiles, uint32_t num_wg) {
+uint32_t tcol_stride(uint32_t num_wg) {
+    return (num_wg + kTcolAlign - 1u) / kTcolAlign * kTcolAlign;
+}
+
+Launch transpose_launch(uint32_t ntiles, uint32_t num_wg) {
     Launch l;
-    l.func = reinterpret_cast<const void*>(&count_kernel);
-    l.block = dim3(64);
-    // about 64 table rows per workgroup
-    l.grid = dim3((ntiles + 63u) / 64u, max(1u, min(64u, (num_wg + 63u) / 64u)));
+    l.func = reinterpret_cast<const void*>(&transpose_kernel);
+    l.block = dim3(256);
+    const uint32_t groups = (ntiles + 1u + 63u) / 64u;
+    const uint32_t row_groups = (num_wg + kTransRows - 1u) / kTransRows;
+    l.grid = dim3(groups * ((row_groups + 7u) / 8u * 8u));  // row groups padded to 8
     l.shared = 0;
     return l;
 }
