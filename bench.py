@@ -173,9 +173,18 @@ def bench_batched(args) -> dict:
     print(f"bench batched: {len(clouds)} clouds, {total_pts} points, {len(views)} views, "
           f"{total_px} px, tuning {tuning}", file=sys.stderr, flush=True)
 
+    # raw library calls with the cameras converted before the timed region
+    # (inputs, like the points); each frame still hands all its cameras to
+    # mm_batch_set_cameras, and each call's status is checked
+    Lb = mm.lib()
+    nviews = len(views)
+    cam_ptrs_b = [mm._fptr(c) for c in frames_cams]  # frames_cams keeps the memory alive
+
     def batch_frame(f):
-        mm.mm_batch_set_cameras(b, 0, frames_cams[f])
-        mm.mm_batch_step_render(b, f)
+        st = (Lb.mm_batch_set_cameras(b, 0, nviews, cam_ptrs_b[f])
+              or Lb.mm_batch_step_render(b, f))
+        if st:
+            raise mm.MMError(st, "batch frame loop", mm.mm_last_error())
 
     for f in range(W):
         batch_frame(f)

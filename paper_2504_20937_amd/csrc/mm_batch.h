@@ -86,7 +86,8 @@ struct Plan {
     TableImage img;
     void* dev_static = nullptr;
     void* dev_frame = nullptr;
-    void* ring[kRing] = {};       // pinned staging of the per-frame image
+    void* ring[kRing] = {};       // pinned, host-coherent staging of the per-frame image
+    void* ring_dev[kRing] = {};   // the same slots' device addresses
     hipEvent_t ring_ev[kRing] = {};
     int ring_next = 0;
     mm::BatchBinArgs bargs{};
@@ -108,7 +109,8 @@ struct Plan {
     mm_status build_graph();
     void free_scratch();
     mm_status next_stamp(hipStream_t s);
-    // Copies the per-frame image (steps, cameras) to the device, in stream order.
+    // Copies the per-frame image (steps, cameras) to the device, in stream
+    // order, with a kernel reading the pinned slot.
     mm_status upload_frame(hipStream_t s);
     mm_status launch_graph(hipStream_t s);
     // Render only: the bin pass without displacement, then the tile passes.

@@ -50,6 +50,7 @@ void Plan::free_scratch() {
     for (int j = 0; j < kRing; ++j) {
         if (ring[j]) (void)hipHostFree(ring[j]);
         ring[j] = nullptr;
+        ring_dev[j] = nullptr;
         if (ring_ev[j]) (void)hipEventDestroy(ring_ev[j]);
         ring_ev[j] = nullptr;
     }
@@ -294,8 +295,10 @@ mm_status Plan::setup(mm_instance inst, const mm_batch_tuning& t) {
     MM_HIP(hipStreamSynchronize(s));
     MM_HIP(hipMalloc(&dev_frame, img.frame.size()));
     for (int j = 0; j < kRing; ++j) {
-        MM_HIP(hipHostMalloc(&ring[j], img.frame.size(), hipHostMallocDefault));
-        MM_HIP(hipEventCreateWithFlags(&ring_ev[j], hipEventDisableTiming));
+        MM_HIP(hipHostMalloc(&ring[j], img.frame.size(), hipHostMallocCoherent));
+        MM_HIP(hipHostGetDevicePointer(&ring_dev[j], ring[j], 0));
+        // marks the upload kernel's reads of slot j done: no cache flush needed
+        MM_HIP(hipEventCreateWithFlags(&ring_ev[j], hipEventDisableTiming | hipEventDisableSystemFence));
     }
     ring_next = 0;
     bind_args(img, static_cast<unsigned char*>(dev_static), static_cast<unsigned char*>(dev_frame),
@@ -341,9 +344,9 @@ mm_status Plan::next_stamp(hipStream_t s) {
 mm_status Plan::upload_frame(hipStream_t s) {
     const int j = ring_next;
     ring_next = (ring_next + 1) % kRing;
-    MM_HIP(hipEventSynchronize(ring_ev[j]));  // the copy that last read slot j is done
+    MM_HIP(hipEventSynchronize(ring_ev[j]));  // the upload that last read slot j is done
     std::memcpy(ring[j], img.frame.data(), img.frame.size());
-    MM_HIP(hipMemcpyAsync(dev_frame, ring[j], img.frame.size(), hipMemcpyHostToDevice, s));
+    MM_HIP(mm::launch_upload(dev_frame, ring_dev[j], img.frame.size(), s));
     MM_HIP(hipEventRecord(ring_ev[j], s));
     return MM_OK;
 }

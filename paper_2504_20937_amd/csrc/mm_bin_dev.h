@@ -4,7 +4,11 @@
 // written out as the chunk's segment of 8-byte records plus one table row of
 // u16 tile start offsets.
 //
-//   record = depth_bits << 32 | local_index << 16 | y_in_tile << 8 | x_in_tile
+//   record = depth_bits << 32 | local_index << 16 | 8 (y_in_tile * side + x_in_tile)
+//
+// (the low half-word is the byte offset of the pixel's key in the tile pass's
+// LDS key block, below 2^15 for tiles up to 64 pixels, so the depth test
+// finds its address with one AND)
 //
 // Larger chunks give the tile pass longer runs per (chunk, tile) and a
 // smaller table, at the cost of LDS per workgroup (8 P + 4 (tiles + 1) bytes).
@@ -136,7 +140,7 @@ __device__ __forceinline__ void bin_view(const BinView& v, uint32_t n, uint32_t 
         const uint32_t slot = atomicAdd(&hist[(uy >> shift) * v.tiles_x + (ux >> shift)], 1u);
         const uint32_t local = static_cast<uint32_t>(k) * NT + tid;
         stage[slot] = (static_cast<uint64_t>(dep[k]) << 32) |
-                      static_cast<uint64_t>((local << 16) | ((uy & mask) << 8) | (ux & mask));
+                      static_cast<uint64_t>((local << 16) | ((((uy & mask) << shift) | (ux & mask)) << 3));
     }
     __syncthreads();
 

@@ -159,6 +159,10 @@ hipError_t launch_point(const PointArgs& a, int dim, int footprint, bool wrap, P
                         hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_fill(uint64_t* keys, uint64_t nkeys, uint64_t value, hipStream_t s);
+// Copies `bytes` from pinned, host-coherent memory (src: its device address,
+// 8-byte aligned) to device memory (dst, 8-byte aligned) with a kernel in
+// stream order: no switch to a copy engine between the kernels around it.
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 // Binned splat. Tile side 1 << shift with shift in {4, 5, 6}; bin workgroups
 // of `threads` in {256, 512, 1024} threads with points per thread in

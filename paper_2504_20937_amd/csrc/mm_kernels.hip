@@ -12,6 +12,8 @@
 //
 // The point kernel with only the displacement phase is also the
 // displace-only step of every splat mode.
+#include <algorithm>
+
 #include "mm_device.h"
 
 namespace mm {
@@ -72,6 +74,20 @@ __global__ __launch_bounds__(256) void fill_kernel(uint64_t* keys, uint64_t n, u
     if (j < n) keys[j] = value;
 }
 
+// Host-staged tables into device memory: 8-byte words read from pinned,
+// host-coherent memory with system-scope loads (always the host's latest
+// writes, never a stale cached line), plus a tail of single bytes.
+__global__ __launch_bounds__(256) void upload_kernel(const uint64_t* src, uint64_t* dst, uint64_t n8,
+                                                     const unsigned char* src_tail,
+                                                     unsigned char* dst_tail, uint32_t tail) {
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * 256u;
+    for (uint64_t j = static_cast<uint64_t>(blockIdx.x) * 256u + threadIdx.x; j < n8; j += stride)
+        dst[j] = __hip_atomic_load(src + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (blockIdx.x == 0 && threadIdx.x < tail)
+        dst_tail[threadIdx.x] = __hip_atomic_load(src_tail + threadIdx.x, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 template <int DIM, int FOOT, bool WRAP>
 const void* pick_phase(Phase phase) {
     switch (phase) {
@@ -122,6 +138,21 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s) {
     ResolveArgs copy = a;
     void* args[] = {&copy};
     return hipLaunchKernel(l.func, l.grid, l.block, args, 0, s);
+}
+
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 7u)
+        return hipErrorInvalidValue;
+    const uint64_t* src8 = static_cast<const uint64_t*>(src);
+    uint64_t* dst8 = static_cast<uint64_t*>(dst);
+    uint64_t n8 = bytes / 8;
+    const unsigned char* src_tail = static_cast<const unsigned char*>(src) + n8 * 8;
+    unsigned char* dst_tail = static_cast<unsigned char*>(dst) + n8 * 8;
+    uint32_t tail = static_cast<uint32_t>(bytes % 8);
+    const dim3 grid(static_cast<uint32_t>(std::min<uint64_t>((n8 + 255) / 256, 64)) + (n8 == 0 ? 1u : 0u));
+    void* args[] = {&src8, &dst8, &n8, &src_tail, &dst_tail, &tail};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&upload_kernel), grid, dim3(256), args, 0, s);
 }
 
 hipError_t launch_fill(uint64_t* keys, uint64_t nkeys, uint64_t value, hipStream_t s) {

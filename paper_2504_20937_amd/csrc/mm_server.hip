@@ -82,7 +82,8 @@ struct Slot {
     std::vector<uint64_t> reqs;
     unsigned char* dev = nullptr;   // device copy of the table images
     size_t dev_bytes = 0;
-    unsigned char* pinned = nullptr;
+    unsigned char* pinned = nullptr;   // host-coherent staging of the table images
+    void* pinned_dev = nullptr;        // its device address
     size_t pinned_bytes = 0;
     uint32_t* stamp_slot = nullptr;
     mmb::TableImage img;
@@ -308,13 +309,16 @@ mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
     if (total > sl.pinned_bytes) {
         if (sl.pinned) (void)hipHostFree(sl.pinned);
         sl.pinned = nullptr;
+        sl.pinned_dev = nullptr;
         sl.pinned_bytes = 0;
-        MM_HIP(hipHostMalloc(reinterpret_cast<void**>(&sl.pinned), total * 2, hipHostMallocDefault));
+        MM_HIP(hipHostMalloc(reinterpret_cast<void**>(&sl.pinned), total * 2, hipHostMallocCoherent));
+        MM_HIP(hipHostGetDevicePointer(&sl.pinned_dev, sl.pinned, 0));
         sl.pinned_bytes = total * 2;
     }
     std::memcpy(sl.pinned, sl.img.stat.data(), stat);
     std::memcpy(sl.pinned + stat, sl.img.frame.data(), frame);
-    MM_HIP(hipMemcpyAsync(sl.dev, sl.pinned, total, hipMemcpyHostToDevice, sl.stream));
+    // a kernel reads the staged tables: the slot's stream stays on the compute queue
+    MM_HIP(mm::launch_upload(sl.dev, sl.pinned_dev, total, sl.stream));
     mmb::bind_args(sl.img, sl.dev, sl.dev + stat, sl.stamp_slot, shift, P, sl.b, sl.t, sl.m);
     if (++stamp == 0) {
         // every older stamp must read as "not this launch": clear all of them

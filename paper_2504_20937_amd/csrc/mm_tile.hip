@@ -67,23 +67,24 @@ __device__ __forceinline__ uint32_t tile_flag(const TileView& v, uint32_t t) {
     return load_flag(&v.active[t]);
 }
 
-// The record's key into its centre pixel of the tile (S x S keys in LDS).
-// A 3x3 footprint is applied afterwards, by a 3x3 minimum over the centre
-// minima (exact: a pixel's key is the minimum over the records centred in
-// its neighbourhood, in any grouping), so every record costs one LDS atomic
-// whatever the footprint.
 // Threads of a tile workgroup (the depth test of one tile or one piece of
-// it). 512 keeps two or three workgroups resident per CU, so one
-// workgroup's table reads and scans overlap another's record stream.
+// it). 512 keeps two workgroups resident per CU, so one workgroup's table
+// reads and scans overlap another's record stream.
 constexpr uint32_t kTileThreads = 512;
 constexpr uint32_t kTileWaves = kTileThreads / 64;
 
+// The record's key into its centre pixel of the tile (S x S keys in LDS; the
+// record's low half-word is the byte offset of the pixel's key). A 3x3
+// footprint is applied afterwards, by a 3x3 minimum over the centre minima
+// (exact: a pixel's key is the minimum over the records centred in its
+// neighbourhood, in any grouping), so every record costs one LDS atomic
+// whatever the footprint.
 template <uint32_t S>
 __device__ __forceinline__ void splat_record(uint64_t* keys, uint64_t r, uint32_t gbase) {
     const uint32_t lo = static_cast<uint32_t>(r);
-    const uint32_t cx = lo & 0xFFu, cy = (lo >> 8) & 0xFFu;
+    uint64_t* key_at = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(keys) + (lo & 0xFFFFu));
     const uint64_t key = (r & 0xFFFFFFFF00000000ull) | static_cast<uint64_t>(gbase + (lo >> 16));
-    atomic_min_lds(&keys[cy * S + cx], key);
+    atomic_min_lds(key_at, key);
 }
 
 // Partial key block (A x A) of the tile from its centre minima: with the 3x3
