@@ -41,7 +41,7 @@ KERNEL_SOURCES = {
 TRAFFIC = {
     "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
                    "tuning": [2, 32, 8, 2, 1024, 0xFFFFFFFF],
-                   "digest": "e246c7a4cda09910", "fetch_kib": 98394.4, "write_kib": 335981.4,
+                   "digest": "c36d3d0c0e523671", "fetch_kib": 98395.2, "write_kib": 335973.1,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 PROFILE_EVERY = 8  # frames per profiled frame in the timed loop
