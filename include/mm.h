@@ -78,6 +78,24 @@ mm_status mm_destroy_instance(mm_instance inst);
 /* Waits until all work enqueued on the instance's stream has finished. */
 mm_status mm_synchronize(mm_instance inst);
 
+/* Compute sections, the paper's prepareViews / updateViews (section
+ * "Synchronization": a simulation's writes to the viewed allocations are
+ * bracketed so that display never reads a half-written state). For a
+ * simulation that writes positions (or other viewed data) on a HIP stream of
+ * its own, `stream` (NULL: the null stream):
+ *   mm_prepare_views: `stream` waits until the work enqueued so far on the
+ *     instance (frames, batches, grids, edge views) has finished, so the
+ *     simulation may then overwrite what that work reads;
+ *   mm_update_views: the instance's later work waits until the work enqueued
+ *     so far on `stream` has finished, so the next frames see the writes.
+ * Work enqueued on the instance between the two calls runs beside the
+ * simulation: the paper's ping-pong scheme, one buffer rendered while the
+ * other is written (two views on two allocations, rendered alternately).
+ * Both calls only enqueue events (no host wait). Servers run on streams of
+ * their own and are not covered. */
+mm_status mm_prepare_views(mm_instance inst, void* stream);
+mm_status mm_update_views(mm_instance inst, void* stream);
+
 /* ------------------------------------------------------------- allocations
  * Section "Allocations": allocLinear takes the native allocator's
  * arguments and returns a plain device pointer that kernels use as usual,

@@ -201,6 +201,8 @@ def _declare(L):
         "mm_get_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
         "mm_profile_begin": ([_vp, C.c_uint32], _status),
         "mm_profile_every": ([_vp, C.c_uint32], _status),
+        "mm_prepare_views": ([_vp, _vp], _status),
+        "mm_update_views": ([_vp, _vp], _status),
         "mm_profile_end": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
                             C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
         "mm_autotune": ([_vp, C.c_uint32, C.POINTER(mm_tuning)], _status),
@@ -289,6 +291,16 @@ def mm_synchronize(inst: int) -> None:
 
 
 # --------------------------------------------------------------- allocations
+def mm_prepare_views(inst: int, stream: int | None = None) -> None:
+    """Start of a compute section: `stream` waits for the instance's work so far."""
+    _check(lib().mm_prepare_views(inst, stream), "mm_prepare_views")
+
+
+def mm_update_views(inst: int, stream: int | None = None) -> None:
+    """End of a compute section: the instance's later work waits for `stream`."""
+    _check(lib().mm_update_views(inst, stream), "mm_update_views")
+
+
 def mm_alloc_linear(inst: int, nbytes: int) -> tuple[int, int]:
     """Returns (device pointer, alloc handle)."""
     ptr, out = _vp(), _vp()

@@ -33,6 +33,9 @@ struct mm_instance_s {
     std::set<mm_server> servers;
     std::set<mm_grid> grids;
     std::set<mm_edges> edges;
+    // compute sections (mm_prepare_views / mm_update_views), created on first use
+    hipEvent_t prep_ev = nullptr;
+    hipEvent_t upd_ev = nullptr;
 };
 
 namespace mmh {

@@ -631,8 +631,35 @@ mm_status mm_destroy_instance(mm_instance inst) {
         if (a->owned) (void)hipFree(a->ptr);
         delete a;
     }
+    for (hipEvent_t e : {inst->prep_ev, inst->upd_ev})
+        if (e) (void)hipEventDestroy(e);
     if (inst->owns_stream) (void)hipStreamDestroy(inst->stream);
     delete inst;
+    return MM_OK;
+}
+
+// Ordering between the instance stream and a simulation's stream on one
+// device: a device-scope release is enough.
+static mm_status section_event(hipEvent_t& e) {
+    if (!e) MM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventReleaseToDevice));
+    return MM_OK;
+}
+
+mm_status mm_prepare_views(mm_instance inst, void* stream) {
+    if (!inst) return fail(MM_ERR_INVALID_ARG, "prepare_views: null instance");
+    DeviceGuard guard(inst->device);
+    MM_TRY(section_event(inst->prep_ev));
+    MM_HIP(hipEventRecord(inst->prep_ev, inst->stream));
+    MM_HIP(hipStreamWaitEvent(static_cast<hipStream_t>(stream), inst->prep_ev, 0));
+    return MM_OK;
+}
+
+mm_status mm_update_views(mm_instance inst, void* stream) {
+    if (!inst) return fail(MM_ERR_INVALID_ARG, "update_views: null instance");
+    DeviceGuard guard(inst->device);
+    MM_TRY(section_event(inst->upd_ev));
+    MM_HIP(hipEventRecord(inst->upd_ev, static_cast<hipStream_t>(stream)));
+    MM_HIP(hipStreamWaitEvent(inst->stream, inst->upd_ev, 0));
     return MM_OK;
 }
 

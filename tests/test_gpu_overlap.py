@@ -129,3 +129,39 @@ def test_overlap_profile_events(rig):
     assert len(sp) == 8 and all(x > 0 for x in sp)
     mm.mm_destroy_view(view)
     mm.mm_free(alloc)
+
+
+def test_compute_sections_ping_pong(rig):
+    """The paper's ping-pong scheme with a simulation on a stream of its own:
+    per frame, mm_prepare_views, the simulation writes buffer W from buffer R
+    on its stream while the view of R is rendered, then mm_update_views;
+    every rendered frame and both buffers match the oracle."""
+    say("case: compute sections, two buffers of 2^20 points, 640x360, 12 frames")
+    torch, mm = rig.torch, rig.mm
+    n, w, h, seed = 1 << 20, 640, 360, 5
+    pts = synth.uniform_cube(n, seed=11)
+    bufs = [rig.cloud(pts)[0], rig.cloud(pts)[0]]
+    allocs = [mm.mm_alloc_wrap(rig.inst, b.data_ptr(), b.numel() * 4) for b in bufs]
+    views = [rig.view(a, n, 3, w, h, 1, seed, 0.0, False, synth.orbit_camera(0, w, h))
+             for a in allocs]
+    for v in views:
+        mm.mm_set_tuning(v, mm.MM_SPLAT_BINNED)
+    sim = torch.cuda.Stream()
+    # the simulation's step k: every coordinate += 2^-10 (k + 1), exact in binary32
+    host = [pts.copy(), pts.copy()]
+    for k in range(12):
+        r, wr = k % 2, (k + 1) % 2
+        cam = synth.orbit_camera(k, w, h)
+        mm.mm_prepare_views(rig.inst, sim.cuda_stream)
+        with torch.cuda.stream(sim):
+            torch.add(bufs[r], (k + 1) * 2.0**-10, out=bufs[wr])
+        mm.mm_set_camera(views[r], cam)
+        mm.mm_render(views[r])  # reads buffer r beside the simulation
+        mm.mm_update_views(rig.inst, sim.cuda_stream)
+        want = oracle.render(host[r], seed, cam, w, h, 1)
+        host[wr] = (host[r] + np.float32((k + 1) * 2.0**-10)).astype(np.float32)
+        got = mm.mm_read_frame(views[r], w, h)
+        assert np.array_equal(got, want), f"frame {k}: {first_diff(got, want)}"
+    torch.cuda.synchronize()
+    for b, ref in zip(bufs, host):
+        assert same_bits(rig.positions(b), ref)
