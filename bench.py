@@ -464,6 +464,41 @@ def bench_edges(args) -> dict:
     }
 
 
+def bench_cobound(args) -> dict:
+    """The ALU co-bound of the bin pass: `mm_cobound` (built beside the
+    library) times the per-point Philox draw, and the draw with the
+    displacement and projection, in the bin kernel's launch shape without the
+    position traffic, and the launch with only its index arithmetic and one
+    store per thread. Reported beside the bin kernel's time from a frame run."""
+    import subprocess
+
+    from paper_2504_20937_amd import build as mmbuild
+
+    if not os.path.exists(mmbuild.COBOUND_EXE):
+        raise SystemExit(f"{mmbuild.COBOUND_EXE} is not built: run __graft_entry__.build()")
+    r = subprocess.run([mmbuild.COBOUND_EXE, str(args.log2n), "50"], capture_output=True,
+                       text=True, timeout=120)
+    if r.returncode != 0:
+        raise SystemExit(f"mm_cobound failed ({r.returncode}): {r.stderr.strip()}")
+    probe = json.loads(r.stdout.strip().splitlines()[-1])
+    n = probe["points"]
+    alu_us = probe["displace_project_us"] - probe["index_store_us"]
+    return {
+        "metric": "bin pass ALU co-bound: per-point displace + project time without memory traffic",
+        "value": alu_us,
+        "unit": "us per launch",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "u32 Philox + f32",
+        "data": "synthetic",
+        "config": {"workload": f"cobound-2^{args.log2n}pts-1024x8", "points": n},
+        "philox_us": probe["philox_us"] - probe["index_store_us"],
+        "displace_project_us": alu_us,
+        "launch_and_store_us": probe["index_store_us"],
+        "probe": probe,
+    }
+
+
 def bench_hostcopy(args) -> dict:
     """The comparison the paper draws: per frame the device displaces the
     cloud, the positions are copied to host memory, and the host renders
@@ -573,12 +608,14 @@ def main() -> int:
     ap.add_argument("--overlap", action="store_true",
                     help="frame: bin frame f while frame f - 1 is drawn (mm_set_frame_overlap)")
     ap.add_argument("--hostcopy-frames", type=int, default=10, help="hostcopy: frames timed")
-    ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy", "grid", "edges"],
+    ap.add_argument("--workload", choices=["frame", "batched", "served", "hostcopy", "grid", "edges",
+                                           "cobound"],
                     default="frame",
                     help="frame: the 2^24-point 1080p frame (default); batched: 64 clouds "
                          "with 1-4 views each in one launch per pass; served: Poisson "
                          "requests from 256 sessions through the server; hostcopy: device "
-                         "displace, copy to host, render on the host cores")
+                         "displace, copy to host, render on the host cores; cobound: the "
+                         "bin pass's per-point ALU work without memory traffic")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: requests per second")
     ap.add_argument("--requests", type=int, default=4000, help="served: requests per run")
     ap.add_argument("--streams", type=int, default=2, help="served: streams")
@@ -593,6 +630,10 @@ def main() -> int:
               "measured on a single MI355X (multi-GPU sharding is a design note, not "
               "built); run with --gpus 1", file=sys.stderr)
         return 2
+
+    if args.workload == "cobound":  # before this process touches the GPU
+        print(json.dumps(bench_cobound(args)), flush=True)
+        return 0
 
     import torch
 

@@ -15,6 +15,8 @@ OUT = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmm.so")
 HOSTCOPY = os.path.join(PKG, "hostcopy")
 HOSTCOPY_LIB = os.path.join(PKG, "libmm_hostcopy.so")
+COBOUND_SRC = os.path.join(PKG, "cobound", "mm_cobound.hip")
+COBOUND_EXE = os.path.join(PKG, "mm_cobound")
 ARCH = "gfx950"
 HIPFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -80,7 +82,21 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("linking libmm.so failed")
     os.replace(tmp, LIB)
     build_hostcopy()
+    build_cobound()
     return LIB
+
+
+def build_cobound() -> str:
+    """The ALU co-bound microbenchmark of the bin pass (an executable; the
+    bench runs it as a child process)."""
+    tmp = COBOUND_EXE + ".tmp"
+    cmd = [hipcc(), *HIPFLAGS, COBOUND_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("building mm_cobound failed")
+    os.replace(tmp, COBOUND_EXE)
+    return COBOUND_EXE
 
 
 def build_hostcopy() -> str:
