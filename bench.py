@@ -40,8 +40,8 @@ KERNEL_SOURCES = {
 }
 TRAFFIC = {
     "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
-                   "tuning": [2, 32, 8, 2, 1024, 0xFFFFFFFF],
-                   "digest": "c36d3d0c0e523671", "fetch_kib": 98395.2, "write_kib": 335973.1,
+                   "tuning": [2, 32, 8, 1, 1024, 0xFFFFFFFF],
+                   "digest": "842eb40bcb9e8825", "fetch_kib": 98395.5, "write_kib": 335978.7,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 PROFILE_EVERY = 8  # frames per profiled frame in the timed loop

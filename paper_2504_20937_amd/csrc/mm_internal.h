@@ -175,6 +175,8 @@ Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t threads, ui
                   uint32_t ntiles);
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits);
 Launch merge_launch(int footprint, int shift, uint32_t ntiles);
+// 1x1 footprint, one split: the tile pass resolves to RGBA8 itself (no merge).
+Launch tile_fused_launch(int shift, uint32_t ntiles);
 Launch seam_launch(int shift, uint32_t ntiles);
 // Load-balanced tile pass: the table made tile-major with the tiles' record
 // totals, the plan, then a persistent grid of tile workgroups over the work

@@ -71,7 +71,6 @@ __device__ __forceinline__ uint32_t tile_flag(const TileView& v, uint32_t t) {
 // it). 512 keeps two workgroups resident per CU, so one workgroup's table
 // reads and scans overlap another's record stream.
 constexpr uint32_t kTileThreads = 512;
-constexpr uint32_t kTileWaves = kTileThreads / 64;
 
 // The record's key into its centre pixel of the tile (S x S keys in LDS; the
 // record's low half-word is the byte offset of the pixel's key). A 3x3
@@ -90,13 +89,13 @@ __device__ __forceinline__ void splat_record(uint64_t* keys, uint64_t r, uint32_
 // Partial key block (A x A) of the tile from its centre minima: with the 3x3
 // footprint, block entry (i, j) is pixel (j - 1, i - 1) of the tile and takes
 // the minimum over centres (cx, cy) in [j - 2, j] x [i - 2, i] inside the tile.
-template <int FOOT, uint32_t S, uint32_t A>
+template <int FOOT, uint32_t S, uint32_t A, uint32_t NT>
 __device__ __forceinline__ void write_part(const uint64_t* keys, uint64_t* part) {
     const uint32_t tid = threadIdx.x;
     if constexpr (FOOT == 1) {
-        for (uint32_t q = tid; q < S * S; q += kTileThreads) part[q] = keys[q];
+        for (uint32_t q = tid; q < S * S; q += NT) part[q] = keys[q];
     } else {
-        for (uint32_t q = tid; q < A * A; q += kTileThreads) {
+        for (uint32_t q = tid; q < A * A; q += NT) {
             const uint32_t i = q / A, j = q % A;
             uint64_t m = kEmptyKey;
 #pragma unroll
@@ -114,7 +113,7 @@ __device__ __forceinline__ void write_part(const uint64_t* keys, uint64_t* part)
     }
 }
 
-template <int FOOT, int SHIFT>
+template <int FOOT, int SHIFT, uint32_t NT = kTileThreads>
 struct TileShape {
     static constexpr uint32_t S = 1u << SHIFT;
     static constexpr uint32_t A = FOOT == 3 ? S + 2 : S;
@@ -123,7 +122,7 @@ struct TileShape {
     // LDS words beside the keys: run offsets (kCol + 1, padded to even), run
     // address bias and index base (2 kCol), the segment's run-start bitmap
     // (kSeg / 32) and the scan's wave sums (2 per wave)
-    static constexpr uint32_t kColLds = (kCol + 2) + 2 * kCol + kSeg / 32 + 2 * kTileWaves;
+    static constexpr uint32_t kColLds = (kCol + 2) + 2 * kCol + kSeg / 32 + 2 * (NT / 64);
 };
 
 // Inclusive scan of two values over the 64 lanes of a wave.
@@ -199,30 +198,33 @@ __device__ __forceinline__ void splat_segment(const uint64_t* seg, uint64_t* key
 }
 
 // Tile t over bin workgroups [w_lo, w_hi): the per-pixel minimum of their
-// records, written as partial key block `piece` of v.part. kTileThreads threads; keys
-// (S * S centre minima) and lds (kColLds words) are LDS. Ends with the block
-// synchronised.
+// records, written as partial key block `piece` of v.part, or with RESOLVE
+// (1x1 footprint, the tile's whole column) resolved to RGBA8 in the frame.
+// NT threads; keys (S * S centre minima) and lds (kColLds words) are LDS.
+// Ends with the block synchronised.
 //
 // Per pass over up to kCol bin workgroups: each thread reads the (start,
 // end) pairs of 4 consecutive workgroups from the table, and a block scan
 // over the non-empty runs gives their flat offsets (roff) and locations. The
 // flat record list is then taken in segments of up to kSeg records: the run
 // starts of a segment are marked in an LDS bitmap, and its 64-record windows
-// are cut into 16 equal ranges, one per wave. A wave's work thus depends on
+// are cut into equal ranges, one per wave. A wave's work thus depends on
 // the records, not on how they fall into runs.
-template <int FOOT, int SHIFT>
+template <int FOOT, int SHIFT, uint32_t NT = kTileThreads, bool RESOLVE = false>
 __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32_t w_lo,
                                            uint32_t w_hi, uint32_t piece, uint32_t P,
                                            uint64_t* keys, uint32_t* lds) {
-    using Sh = TileShape<FOOT, SHIFT>;
+    static_assert(!RESOLVE || FOOT == 1, "a 3x3 footprint needs the seam pass");
+    using Sh = TileShape<FOOT, SHIFT, NT>;
     constexpr uint32_t S = Sh::S, A = Sh::A, kCol = Sh::kCol, kSeg = Sh::kSeg;
-    constexpr uint32_t kPer = kCol / kTileThreads;  // bin workgroups per thread and pass
+    constexpr uint32_t kWaves = NT / 64;
+    constexpr uint32_t kPer = kCol / NT;  // bin workgroups per thread and pass
     uint32_t* roff = lds;
     uint2* runs = reinterpret_cast<uint2*>(lds + kCol + 2);
     uint32_t* bits = lds + kCol + 2 + 2 * kCol;
     uint32_t* wsum = bits + kSeg / 32;  // [0, waves): records, [waves, 2 waves): runs
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
-    for (uint32_t q = tid; q < S * S; q += kTileThreads) keys[q] = kEmptyKey;
+    for (uint32_t q = tid; q < S * S; q += NT) keys[q] = kEmptyKey;
     const uint32_t stride = v.ntiles + 1u;
 
     for (uint32_t base = w_lo; base < w_hi; base += kCol) {
@@ -260,13 +262,13 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
         wave_scan2(ic, ir, lane);
         if (lane == 63u) {
             wsum[wave] = ic;
-            wsum[kTileWaves + wave] = ir;
+            wsum[kWaves + wave] = ir;
         }
         __syncthreads();
         uint32_t total = 0, nruns = 0, oc = ic - tc, orr = ir - tr;
 #pragma unroll
-        for (uint32_t w = 0; w < kTileWaves; ++w) {
-            const uint32_t c = wsum[w], r = wsum[kTileWaves + w];
+        for (uint32_t w = 0; w < kWaves; ++w) {
+            const uint32_t c = wsum[w], r = wsum[kWaves + w];
             total += c;
             nruns += r;
             oc += w < wave ? c : 0u;
@@ -289,23 +291,35 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
             const uint32_t len = min(kSeg, total - s0);
             const uint32_t words = ((len + 63u) >> 6) * 2u;
             __syncthreads();  // runs written / previous segment done with the bitmap
-            for (uint32_t q = tid; q < words; q += kTileThreads) bits[q] = 0u;
+            for (uint32_t q = tid; q < words; q += NT) bits[q] = 0u;
             __syncthreads();
-            for (uint32_t k = tid; k < nruns; k += kTileThreads) {
+            for (uint32_t k = tid; k < nruns; k += NT) {
                 const uint32_t pos = roff[k] - s0;
                 if (pos < len) atomicOr(&bits[pos >> 5], 1u << (pos & 31u));
             }
             __syncthreads();
             const uint32_t nwin = (len + 63u) >> 6;
-            const uint32_t r0 = s0 + (nwin * wave / kTileWaves) * 64u;
-            const uint32_t r1 = s0 + min(len, (nwin * (wave + 1u) / kTileWaves) * 64u);
+            const uint32_t r0 = s0 + (nwin * wave / kWaves) * 64u;
+            const uint32_t r1 = s0 + min(len, (nwin * (wave + 1u) / kWaves) * 64u);
             if (r0 < r1)
                 splat_segment<S, 12>(seg, keys, roff, runs,
                                      reinterpret_cast<const uint64_t*>(bits), nruns, s0, r0, r1);
         }
     }
     __syncthreads();
-    write_part<FOOT, S, A>(keys, v.part + static_cast<uint64_t>(piece) * (A * A));
+    if constexpr (RESOLVE) {
+        const uint32_t x0 = (t % v.tiles_x) << SHIFT, y0 = (t / v.tiles_x) << SHIFT;
+        const uint32_t wt = min(S, v.width - x0), ht = min(S, v.height - y0);
+        uint32_t* out = v.colour + static_cast<uint64_t>(y0) * v.width + x0;
+        for (uint32_t q = tid; q < S * S; q += NT) {
+            const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
+            if (lx < wt && ly < ht)
+                out[static_cast<uint64_t>(ly) * v.width + lx] =
+                    pixel_colour(keys[q], v.seed_lo, v.seed_hi, v.pal);
+        }
+    } else {
+        write_part<FOOT, S, A, NT>(keys, v.part + static_cast<uint64_t>(piece) * (A * A));
+    }
     __syncthreads();
 }
 
@@ -329,6 +343,38 @@ __global__ __launch_bounds__(kTileThreads) void tile_kernel(TileArgs a) {
     if (t >= a.v.ntiles) return;
     if (tile_flag(a.v, t) != *a.stamp_in) return;  // nothing to draw
     tile_split<FOOT, SHIFT>(a.v, t, z, a.points_per_wg, keys, col);
+}
+
+// One workgroup per tile for the 1x1 footprint: the tile's whole column,
+// resolved to RGBA8 in place (no partial blocks, no merge pass). 1024 threads
+// give a dense tile the issue rate that two workgroups of a split would. A
+// tile with nothing to draw is cleared if the previous frame drew it (or
+// every frame, with full_clear), as the merge pass does.
+constexpr uint32_t kFusedThreads = 1024;
+
+template <int SHIFT>
+__global__ __launch_bounds__(kFusedThreads) void tile_fused_kernel(TileArgs a) {
+    using Sh = TileShape<1, SHIFT, kFusedThreads>;
+    constexpr uint32_t S = Sh::S;
+    __shared__ uint64_t keys[S * S];
+    __shared__ uint32_t col[Sh::kColLds];
+    uint32_t t, z;
+    tile_of_block(blockIdx.x, 1u, t, z);
+    if (t >= a.v.ntiles) return;
+    const uint32_t stamp = *a.stamp_in, flag = tile_flag(a.v, t);
+    if (flag != stamp) {
+        if (flag == stamp - 1u || a.v.full_clear) {
+            const uint32_t x0 = (t % a.v.tiles_x) << SHIFT, y0 = (t / a.v.tiles_x) << SHIFT;
+            const uint32_t wt = min(S, a.v.width - x0), ht = min(S, a.v.height - y0);
+            uint32_t* out = a.v.colour + static_cast<uint64_t>(y0) * a.v.width + x0;
+            for (uint32_t q = threadIdx.x; q < S * S; q += kFusedThreads) {
+                const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
+                if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * a.v.width + lx] = 0u;
+            }
+        }
+        return;
+    }
+    tile_range<1, SHIFT, kFusedThreads, true>(a.v, t, 0u, a.v.num_wg, t, a.points_per_wg, keys, col);
 }
 
 // Load-balanced tile pass. The transpose kernel copies the table tile-major
@@ -726,6 +772,19 @@ Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits) {
     l.func = footprint == 3 ? pick_tile<3>(shift, false) : pick_tile<1>(shift, false);
     l.block = dim3(kTileThreads);
     l.grid = dim3((ntiles + 511u) / 512u * 512u * splits);  // whole runs of 8 XCDs x 64 tiles
+    l.shared = 0;
+    return l;
+}
+
+Launch tile_fused_launch(int shift, uint32_t ntiles) {
+    Launch l;
+    switch (shift) {
+        case 4: l.func = reinterpret_cast<const void*>(&tile_fused_kernel<4>); break;
+        case 5: l.func = reinterpret_cast<const void*>(&tile_fused_kernel<5>); break;
+        default: l.func = reinterpret_cast<const void*>(&tile_fused_kernel<6>); break;
+    }
+    l.block = dim3(kFusedThreads);
+    l.grid = dim3((ntiles + 511u) / 512u * 512u);  // whole runs of 8 XCDs x 64 tiles
     l.shared = 0;
     return l;
 }

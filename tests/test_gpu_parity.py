@@ -36,7 +36,8 @@ BINNED = (2, 0, 0, 0, 0, 0)
 MODES = [DIRECT, BINNED]
 SHAPES = [DIRECT, (2, 16, 4, 1, 256, ST), (2, 32, 8, 4, 256, ST), (2, 64, 16, 2, 256, ST),
           (2, 32, 4, 8, 256, ST), (2, 32, 16, 2, 512, ST), (2, 32, 16, 0, 1024, 1024),
-          (2, 64, 8, 0, 1024, 8192), (2, 16, 4, 0, 512, 2048), (2, 32, 8, 0, 256, 4096)]
+          (2, 64, 8, 0, 1024, 8192), (2, 16, 4, 0, 512, 2048), (2, 32, 8, 0, 256, 4096),
+          (2, 32, 8, 1, 1024, ST), (2, 64, 8, 1, 1024, ST)]
 
 
 def _ids(modes):
@@ -372,6 +373,14 @@ def test_tuning_choices_and_validation(rig):
     view = rig.view(alloc, 5000, 3, 1920, 1080, 1, 0, 0.001, False, cam)
     # 5000 points: one bin workgroup, so one workgroup per tile in the depth test
     assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST)
+    # 2^21 points (256 bin workgroups): the 1x1 footprint keeps one workgroup per
+    # tile (which resolves the tile itself), the 3x3 footprint takes two splits
+    n2 = 1 << 21
+    dev2, alloc2 = rig.cloud(synth.uniform_cube(n2, seed=1))
+    v1 = rig.view(alloc2, n2, 3, 1920, 1080, 1, 0, 0.001, False, cam)
+    assert mm.mm_get_tuning(v1) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST)
+    v3 = rig.view(alloc2, n2, 3, 1920, 1080, 3, 0, 0.001, False, cam)
+    assert mm.mm_get_tuning(v3) == (mm.MM_SPLAT_BINNED, 32, 8, 2, 1024, ST)
     for bad, status in [((2, 128, 16, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
                         ((2, 32, 3, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
                         ((2, 32, 16, 3, 0, ST), mm.MM_ERR_INVALID_ARG),
