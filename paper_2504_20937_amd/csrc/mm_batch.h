@@ -58,9 +58,11 @@ struct Node {
 // Tiles, bin workgroups and splits of every view (splits 0: by cloud size).
 void shape_views(std::vector<PlanView>& views, const std::vector<Cloud>& clouds, uint32_t side,
                  uint32_t P, uint32_t splits);
-// Work tables of a launch; views grouped by cloud, their scratch set.
+// Work tables of a launch; views grouped by cloud, their scratch set. With
+// the 1x1 footprint, views of one split get no merge items (the tile pass
+// resolves them).
 mm_status build_tables(const std::vector<Cloud>& clouds, const std::vector<PlanView>& views,
-                       uint32_t P, TableImage& out);
+                       uint32_t P, uint32_t footprint, TableImage& out);
 // Argument blocks over device copies of the two images.
 void bind_args(const TableImage& img, const unsigned char* dstat, const unsigned char* dframe,
                uint32_t* stamp_slot, uint32_t shift, uint32_t P, mm::BatchBinArgs& b,

@@ -131,7 +131,7 @@ void shape_views(std::vector<PlanView>& views, const std::vector<Cloud>& clouds,
 }
 
 mm_status build_tables(const std::vector<Cloud>& clouds, const std::vector<PlanView>& views,
-                       uint32_t P, TableImage& out) {
+                       uint32_t P, uint32_t footprint, TableImage& out) {
     for (size_t i = 1; i < views.size(); ++i)
         if (views[i].cloud < views[i - 1].cloud)
             return fail(MM_ERR_INVALID_ARG, "batch: views are not grouped by cloud");
@@ -178,8 +178,10 @@ mm_status build_tables(const std::vector<Cloud>& clouds, const std::vector<PlanV
     }
     std::vector<uint2> tile_items, merge_items;
     xcd_tile_items(views, tile_items);
+    // with the 1x1 footprint a view of one split is resolved by the tile pass
     for (uint32_t vi = 0; vi < views.size(); ++vi)
-        for (uint32_t tt = 0; tt < views[vi].ntiles; ++tt) merge_items.push_back(make_uint2(vi, tt << 3));
+        if (footprint != 1 || views[vi].splits != 1)
+            for (uint32_t tt = 0; tt < views[vi].ntiles; ++tt) merge_items.push_back(make_uint2(vi, tt << 3));
     out.n_bin = static_cast<uint32_t>(bin_items.size());
     out.n_disp = static_cast<uint32_t>(disp_items.size());
     out.n_tile = static_cast<uint32_t>(tile_items.size());
@@ -289,7 +291,7 @@ mm_status Plan::setup(mm_instance inst, const mm_batch_tuning& t) {
     if (e != hipSuccess) return hip_fail(e, "batch scratch buffers");
     stamp = 0;
 
-    MM_TRY(build_tables(clouds, views, P, img));
+    MM_TRY(build_tables(clouds, views, P, footprint, img));
     MM_HIP(hipMalloc(&dev_static, img.stat.size()));
     MM_HIP(hipMemcpyAsync(dev_static, img.stat.data(), img.stat.size(), hipMemcpyHostToDevice, s));
     MM_HIP(hipStreamSynchronize(s));

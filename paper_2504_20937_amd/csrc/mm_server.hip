@@ -296,7 +296,7 @@ mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
         views.push_back(v);
     }
     mmb::shape_views(views, cl, side, P, desc.tuning.splits);
-    MM_TRY(mmb::build_tables(cl, views, P, sl.img));
+    MM_TRY(mmb::build_tables(cl, views, P, desc.footprint, sl.img));
     const size_t stat = sl.img.stat.size(), frame = sl.img.frame.size();
     const size_t total = stat + frame;
     if (total > sl.dev_bytes) {

@@ -113,6 +113,20 @@ __device__ __forceinline__ void write_part(const uint64_t* keys, uint64_t* part)
     }
 }
 
+// Sets tile t's pixels to 0 (nothing drawn): pixels q = first, first + step, ...
+template <int SHIFT>
+__device__ __forceinline__ void clear_tile(const TileView& v, uint32_t t, uint32_t first,
+                                           uint32_t step) {
+    constexpr uint32_t S = 1u << SHIFT;
+    const uint32_t x0 = (t % v.tiles_x) << SHIFT, y0 = (t / v.tiles_x) << SHIFT;
+    const uint32_t wt = min(S, v.width - x0), ht = min(S, v.height - y0);
+    uint32_t* out = v.colour + static_cast<uint64_t>(y0) * v.width + x0;
+    for (uint32_t q = first; q < S * S; q += step) {
+        const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
+        if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * v.width + lx] = 0u;
+    }
+}
+
 template <int FOOT, int SHIFT, uint32_t NT = kTileThreads>
 struct TileShape {
     static constexpr uint32_t S = 1u << SHIFT;
@@ -363,15 +377,7 @@ __global__ __launch_bounds__(kFusedThreads) void tile_fused_kernel(TileArgs a) {
     if (t >= a.v.ntiles) return;
     const uint32_t stamp = *a.stamp_in, flag = tile_flag(a.v, t);
     if (flag != stamp) {
-        if (flag == stamp - 1u || a.v.full_clear) {
-            const uint32_t x0 = (t % a.v.tiles_x) << SHIFT, y0 = (t / a.v.tiles_x) << SHIFT;
-            const uint32_t wt = min(S, a.v.width - x0), ht = min(S, a.v.height - y0);
-            uint32_t* out = a.v.colour + static_cast<uint64_t>(y0) * a.v.width + x0;
-            for (uint32_t q = threadIdx.x; q < S * S; q += kFusedThreads) {
-                const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
-                if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * a.v.width + lx] = 0u;
-            }
-        }
+        if (flag == stamp - 1u || a.v.full_clear) clear_tile<SHIFT>(a.v, t, threadIdx.x, kFusedThreads);
         return;
     }
     tile_range<1, SHIFT, kFusedThreads, true>(a.v, t, 0u, a.v.num_wg, t, a.points_per_wg, keys, col);
@@ -543,7 +549,22 @@ __global__ __launch_bounds__(kTileThreads) void batch_tile_kernel(BatchTileArgs 
         if (item.x == kPadItem) continue;
         const TileView v = load_uniform(&a.views[item.x]);
         const uint32_t t = item.y >> 3, z = item.y & 7u;
-        if (tile_flag(v, t) != stamp) continue;
+        // 1x1 footprint with one split: the tile is resolved here (its view
+        // has no merge items), so a tile not drawn is cleared here too
+        const bool resolve = FOOT == 1 && v.splits == 1u;
+        const uint32_t flag = tile_flag(v, t);
+        if (flag != stamp) {
+            if (resolve && (flag == stamp - 1u || v.full_clear))
+                clear_tile<SHIFT>(v, t, threadIdx.x, kTileThreads);
+            continue;
+        }
+        if constexpr (FOOT == 1) {
+            if (resolve) {
+                tile_range<1, SHIFT, kTileThreads, true>(v, t, 0u, v.num_wg, t, a.points_per_wg, keys,
+                                                         col);
+                continue;
+            }
+        }
         tile_split<FOOT, SHIFT>(v, t, z, a.points_per_wg, keys, col);
     }
 }
@@ -565,12 +586,7 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
     uint32_t* out = v.colour + static_cast<uint64_t>(y0) * v.width + x0;
     const uint32_t flag = tile_flag(v, t);
     if (flag != stamp) {
-        if (flag == stamp - 1u || v.full_clear) {
-            for (uint32_t q = tid; q < S * S; q += step) {
-                const uint32_t lx = q & (S - 1u), ly = q >> SHIFT;
-                if (lx < wt && ly < ht) out[static_cast<uint64_t>(ly) * v.width + lx] = 0u;
-            }
-        }
+        if (flag == stamp - 1u || v.full_clear) clear_tile<SHIFT>(v, t, tid, step);
         return;
     }
     // the tile's partial blocks: its pieces, or its `splits` static splits
