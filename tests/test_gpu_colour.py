@@ -11,8 +11,9 @@ from gpu_util import Rig, first_diff, say
 pytestmark = pytest.mark.gpu
 
 ST = 0xFFFFFFFF
-MODES = [(1, 0, 0, 0, 0, 0), (2, 32, 8, 2, 1024, ST), (2, 64, 8, 0, 512, 4096)]
-IDS = ["direct", "binned-t32-z2", "binned-t64-balanced"]
+MODES = [(1, 0, 0, 0, 0, 0), (2, 32, 8, 2, 1024, ST), (2, 64, 8, 0, 512, 4096),
+         (2, 32, 8, 1, 1024, ST)]
+IDS = ["direct", "binned-t32-z2", "binned-t64-balanced", "binned-t32-fused"]
 
 
 @pytest.fixture(scope="module")
