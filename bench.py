@@ -82,7 +82,21 @@ def cpu_model() -> str:
 
 def make_points(n: int, dist: str) -> np.ndarray:
     import synth
+    if dist == "square":
+        return synth.uniform_square(n, 0)
     return synth.uniform_cube(n, 0) if dist == "uniform" else synth.gaussian_mixture(n, 0)
+
+
+def frame_setup(dist: str):
+    """(dim, amplitude, wrap) of a frame workload: the 2D square folds its
+    points into [-1, 1)^2 with steps of up to 0.005; the 3D clouds move freely
+    by up to 0.001 per step."""
+    return (2, 0.005, True) if dist == "square" else (3, 0.001, False)
+
+
+def frame_camera(dist: str, f: int, w: int, h: int):
+    import synth
+    return synth.IDENTITY if dist == "square" else synth.orbit_camera(f, w, h)
 
 
 def cpu_baseline(n, w, h, frames, dist="uniform", footprint=1):
@@ -94,11 +108,12 @@ def cpu_baseline(n, w, h, frames, dist="uniform", footprint=1):
     m = min(n, 1 << 24)
     pts = make_points(n, dist)[:m].copy() if m < n else make_points(n, dist)
     depth = oracle.new_depth(w, h)
-    cams = [synth.orbit_camera(f, w, h) for f in range(frames)]
+    _, amp, wrap = frame_setup(dist)
+    cams = [frame_camera(dist, f, w, h) for f in range(frames)]
     oracle.lib()
     t0 = time.perf_counter()
     for f in range(frames):
-        oracle.step_render(pts, 0, f, 0.001, False, cams[f], w, h, footprint, depth)
+        oracle.step_render(pts, 0, f, amp, wrap, cams[f], w, h, footprint, depth)
     dt = time.perf_counter() - t0
     what = "full frames" if m == n else f"frames of the first 2^24 of the 2^{int(np.log2(n))} points"
     return {"value": m * frames / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
@@ -590,8 +605,9 @@ def main() -> int:
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--cpu-frames", type=int, default=48)
-    ap.add_argument("--dist", choices=["uniform", "mixture"], default="uniform",
-                    help="frame: uniform cube or mixture of 32 Gaussians (sigma 0.02)")
+    ap.add_argument("--dist", choices=["uniform", "mixture", "square"], default="uniform",
+                    help="frame: uniform cube, mixture of 32 Gaussians (sigma 0.02), or the 2D "
+                         "square [-1, 1)^2 with wrap (orthographic)")
     ap.add_argument("--footprint", type=int, choices=[1, 3], default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--splat", choices=["auto", "direct", "binned"], default="auto")
@@ -672,12 +688,13 @@ def main() -> int:
     pts = make_points(n, args.dist)
     dev = torch.from_numpy(pts).cuda()
     del pts
-    cams = np.stack([synth.orbit_camera(f, w, h) for f in range(W + K)])
+    dim, amp, wrap = frame_setup(args.dist)
+    cams = np.stack([frame_camera(args.dist, f, w, h) for f in range(W + K)])
     stream = torch.cuda.current_stream()
     inst = mm.mm_create_instance(0, stream.cuda_stream)
     alloc = mm.mm_alloc_wrap(inst, dev.data_ptr(), dev.numel() * 4)
-    view = mm.mm_create_view(inst, mm.make_view_desc(alloc, n, 3, w, h, args.footprint, 0, 0.001,
-                                                     False, cams[0]))
+    view = mm.mm_create_view(inst, mm.make_view_desc(alloc, n, dim, w, h, args.footprint, 0, amp,
+                                                     wrap, cams[0]))
     splat = {"auto": mm.MM_SPLAT_AUTO, "direct": mm.MM_SPLAT_DIRECT,
              "binned": mm.MM_SPLAT_BINNED}[args.splat]
     if args.autotune:
@@ -730,11 +747,12 @@ def main() -> int:
     mm.mm_free(alloc)
     mm.mm_destroy_instance(inst)
 
-    point_bytes = POINT_BYTES * n
+    point_bytes = (8 if dim == 2 else 12) * 2 * n  # read + write of each position
     frame_bytes = point_bytes + PIXEL_BYTES * w * h
     splat_avg = float(np.mean(splat_ms))
     achieved = point_bytes / (splat_avg * 1e-3) / 1e9
-    workload = (f"3d-{args.dist}-2^{args.log2n}pts-{w}x{h}-orbit-1deg"
+    workload = ((f"2d-square-2^{args.log2n}pts-{w}x{h}-wrap" if dim == 2 else
+                 f"3d-{args.dist}-2^{args.log2n}pts-{w}x{h}-orbit-1deg")
                 + (f"-{args.footprint}x{args.footprint}" if args.footprint != 1 else ""))
     out = {
         "metric": METRIC,
@@ -751,7 +769,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": workload,
                    "points": n, "width": w, "height": h, "footprint": args.footprint,
-                   "amplitude": 0.001,
+                   "amplitude": amp, "wrap": wrap,
                    "graph": ("bin of frame f beside the draw of frame f - 1 (two streams)"
                              if args.overlap else "one hipGraph per frame"),
                    "colour": "256-entry palette, 1-byte indices" if args.palette else "index hash",

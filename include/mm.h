@@ -192,8 +192,9 @@ mm_status mm_set_colour(mm_view view, const mm_colour_desc* desc);
  * frames are still bit-identical to the serial path's. Every tile not drawn
  * in a frame is cleared. on = 0 returns to the serial frame graph.
  * Reallocates the view's scratch (a second set of records, table and tile
- * stamps) and synchronises. MM_ERR_UNSUPPORTED when the view's splat is not
- * binned; mm_set_tuning to a direct splat is then refused while it is on. */
+ * stamps) and synchronises. A view whose splat was left on auto switches to
+ * the binned splat (auto shapes); MM_ERR_UNSUPPORTED when the direct splat
+ * was asked for; mm_set_tuning to a direct splat is refused while it is on. */
 mm_status mm_set_frame_overlap(mm_view view, uint32_t on);
 
 /* Overlapped views: draws the frame of the last mm_step_render (the pending
@@ -222,7 +223,9 @@ mm_status mm_read_frame(mm_view view, void* host_rgba, size_t bytes);
  *    per-pixel minimum of their share in LDS, a merge pass combines them and
  *    writes RGBA8 directly (3x3 footprints merge tile seams in a last pass).
  *    No global atomics.
- *  MM_SPLAT_AUTO: binned when the screen fits the tile table, else direct. */
+ *  MM_SPLAT_AUTO: direct for a cloud of at most 2^18 points on a screen of
+ *    at most 2^21 pixels (the binned path's fixed cost per frame dominates
+ *    there), else binned when the screen fits the tile table, else direct. */
 #define MM_SPLAT_AUTO 0u
 #define MM_SPLAT_DIRECT 1u
 #define MM_SPLAT_BINNED 2u

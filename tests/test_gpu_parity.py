@@ -371,7 +371,10 @@ def test_tuning_choices_and_validation(rig):
     dev, alloc = rig.cloud(pts)
     cam = synth.orbit_camera(0, 1920, 1080)
     view = rig.view(alloc, 5000, 3, 1920, 1080, 1, 0, 0.001, False, cam)
-    # 5000 points: one bin workgroup, so one workgroup per tile in the depth test
+    # 5000 points on a 1080p screen: the direct splat (a small cloud)
+    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_DIRECT, 0, 0, 0, 0, 0)
+    # binned by request: one bin workgroup, so one workgroup per tile in the depth test
+    mm.mm_set_tuning(view, mm.MM_SPLAT_BINNED)
     assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST)
     # 2^21 points (256 bin workgroups): the 1x1 footprint keeps one workgroup per
     # tile (which resolves the tile itself), the 3x3 footprint takes two splits
