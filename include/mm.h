@@ -221,7 +221,8 @@ mm_status mm_read_frame(mm_view view, void* host_rgba, size_t bytes);
  *  MM_SPLAT_BINNED: each workgroup sorts its points by screen tile in LDS
  *    and writes 8-byte records; then `splits` workgroups per tile take the
  *    per-pixel minimum of their share in LDS, a merge pass combines them and
- *    writes RGBA8 directly (3x3 footprints merge tile seams in a last pass).
+ *    writes RGBA8 directly (3x3 footprints merge tile seams in a last pass;
+ *    a 1x1 footprint with one split resolves each tile in the same pass).
  *    No global atomics.
  *  MM_SPLAT_AUTO: direct for a cloud of at most 2^18 points on a screen of
  *    at most 2^21 pixels (the binned path's fixed cost per frame dominates
@@ -235,7 +236,10 @@ typedef struct {
     uint32_t tile;              /* binned tile side: 16, 32 or 64 pixels; 0 = auto */
     uint32_t points_per_thread; /* binned: 4, 8 or 16 points per bin thread; 0 = auto */
     uint32_t splits;            /* binned: workgroups per tile in the depth test, 1, 2, 4
-                                   or 8 (each takes a share of the points); 0 = auto */
+                                   or 8 (each takes a share of the points); with the 1x1
+                                   footprint, 1 resolves each tile in the same pass (no
+                                   merge pass); 0 = auto (1x1: 1; 3x3: 2 from 256 bin
+                                   workgroups, else 1) */
     uint32_t bin_threads;       /* binned: threads of a bin workgroup, 256, 512 or 1024
                                    (a chunk is bin_threads * points_per_thread points);
                                    0 = auto */
