@@ -339,12 +339,12 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
 
 // Split z of tile t: bin workgroups [num_wg * z / splits, num_wg * (z + 1) /
 // splits), partial block t * splits + z.
-template <int FOOT, int SHIFT>
+template <int FOOT, int SHIFT, uint32_t NT = kTileThreads>
 __device__ __forceinline__ void tile_split(const TileView& v, uint32_t t, uint32_t z, uint32_t P,
                                            uint64_t* keys, uint32_t* col) {
     const uint32_t w_lo = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * z / v.splits);
     const uint32_t w_hi = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * (z + 1) / v.splits);
-    tile_range<FOOT, SHIFT>(v, t, w_lo, w_hi, t * v.splits + z, P, keys, col);
+    tile_range<FOOT, SHIFT, NT>(v, t, w_lo, w_hi, t * v.splits + z, P, keys, col);
 }
 
 template <int FOOT, int SHIFT>
@@ -545,14 +545,6 @@ __global__ __launch_bounds__(kTileThreads) void tile_list_kernel(TileArgs a) {
 // 512 threads).
 constexpr uint32_t kBatchThreads = 256;
 
-template <int FOOT, int SHIFT, uint32_t NT>
-__device__ __forceinline__ void tile_split_nt(const TileView& v, uint32_t t, uint32_t z, uint32_t P,
-                                              uint64_t* keys, uint32_t* col) {
-    const uint32_t w_lo = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * z / v.splits);
-    const uint32_t w_hi = static_cast<uint32_t>(static_cast<uint64_t>(v.num_wg) * (z + 1) / v.splits);
-    tile_range<FOOT, SHIFT, NT>(v, t, w_lo, w_hi, t * v.splits + z, P, keys, col);
-}
-
 template <int FOOT, int SHIFT>
 __global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(BatchTileArgs a) {
     using Sh = TileShape<FOOT, SHIFT, kBatchThreads>;
@@ -580,7 +572,7 @@ __global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(BatchTileArgs
                 continue;
             }
         }
-        tile_split_nt<FOOT, SHIFT, kBatchThreads>(v, t, z, a.points_per_wg, keys, col);
+        tile_split<FOOT, SHIFT, kBatchThreads>(v, t, z, a.points_per_wg, keys, col);
     }
 }
 
