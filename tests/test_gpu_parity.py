@@ -178,6 +178,33 @@ def test_smallest_screen_and_everything_culled(rig, mode):
     assert not mm.mm_read_frame(view, 32, 32).any()
 
 
+CLEAR_MODES = [DIRECT, BINNED, (2, 32, 8, 1, 1024, ST), (2, 32, 8, 2, 1024, ST),
+               (2, 64, 8, 0, 512, 4096)]
+
+
+@pytest.mark.parametrize("mode", CLEAR_MODES, ids=_ids(CLEAR_MODES))
+def test_tiles_drawn_then_empty_are_cleared(rig, mode):
+    say("case: draw, look away (nothing drawn: an empty frame), look back; 2^18 points 640x360")
+    mm = rig.mm
+    n, w, h, seed = 1 << 18, 640, 360, 4
+    pts = synth.uniform_cube(n, seed=8)
+    dev, alloc = rig.cloud(pts)
+    cam = synth.orbit_camera(0, w, h)
+    away = synth.look_at_perspective((0.5, 0.5, 3.0), (0.5, 0.5, 6.0), (0, 1, 0), 60.0, w / h)
+    view = rig.view(alloc, n, 3, w, h, 1, seed, 0.001, False, cam)
+    mm.mm_set_tuning(view, *mode)
+    ref = pts.copy()
+    for s, m in enumerate([cam, away, away, cam]):
+        mm.mm_set_camera(view, m)
+        mm.mm_step_render(view, s)
+        want = oracle.step_render(ref, seed, s, 0.001, False, m, w, h, 1)
+        got = mm.mm_read_frame(view, w, h)
+        assert np.array_equal(got, want), f"frame {s}: {first_diff(got, want)}"
+        if m is away:
+            assert not got.any()
+    assert same_bits(rig.positions(dev), ref)
+
+
 @pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
 def test_2d_points_on_pixel_edges_and_borders(rig, mode):
     say("case: 2D points on pixel edges, corners and just inside/outside the box")
