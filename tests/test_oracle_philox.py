@@ -1,10 +1,12 @@
-"""Pin the oracle's Philox4x32-10 against two independent implementations.
+"""Pin the oracle's Philox4x32-10 against two independent implementations
+and the published known-answer vectors.
 
 The oracle writes Philox from its published definition (Salmon et al.,
 SC'11). Here it must agree, word for word, with PyTorch's ATen
 ``philox_engine`` and with rocRAND's ``philox4x32_10_engine``, both compiled
 from their source headers, on a million random (counter, key) pairs plus
-edge counters. A wrong multiplier, a swapped output word, a missing key bump
+edge counters, and it must give the generator's published known-answer
+vectors. A wrong multiplier, a swapped output word, a missing key bump
 or a wrong round count fails this.
 """
 import os
@@ -107,3 +109,15 @@ def test_philox_output_words_are_uniform():
     assert chi2 < 350.0  # 255 dof: p(chi2 > 350) < 1e-4
     bits = np.unpackbits(out.view(np.uint8)).reshape(-1, 32).mean(axis=0)
     assert np.all(np.abs(bits - 0.5) < 0.005)
+
+
+def test_philox_known_answer_vectors():
+    """The published known-answer vectors of Philox4x32-10 (Salmon et al.,
+    SC'11), stored under ``tests/golden/``: all-zero, all-ones and the
+    digits-of-pi counter and key."""
+    path = os.path.join(HERE, "golden", "philox4x32_10_kat.txt")
+    rows = [line.split() for line in open(path) if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    v = np.array([[int(w, 16) for w in r] for r in rows], dtype=np.uint64).astype(np.uint32)
+    out = oracle.philox4x32_10(np.ascontiguousarray(v[:, 0:4]), np.ascontiguousarray(v[:, 4:6]))
+    np.testing.assert_array_equal(out, v[:, 6:10])
