@@ -7,9 +7,11 @@ fov 60 deg, 1 deg per frame), then resolves RGBA8. One hipGraph per frame.
 Positions start resident in HBM; nothing crosses PCIe in the timed region.
 
 Prints ONE JSON line: throughput in Gpoints/s (value), frames/s, p50/p99
-frame time from HIP events recorded inside the frame graph, the roofline of
-the dominant kernel (the point kernel), and the CPU oracle timed on a
-bounded sample of the same workload.
+frame time from HIP events on the frame stream before every timed frame and
+after the last, the roofline of the dominant kernel (the bin kernel, timed
+by events inside the frame graph on one frame in eight), the whole frame's
+roofline, the host it ran on, and the CPU oracle timed on a bounded sample
+of the same workload.
 """
 from __future__ import annotations
 
@@ -40,8 +42,8 @@ KERNEL_SOURCES = {
 }
 TRAFFIC = {
     "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
-                   "tuning": [2, 32, 8, 1, 1024, 0xFFFFFFFF],
-                   "digest": "842eb40bcb9e8825", "fetch_kib": 98395.5, "write_kib": 335978.7,
+                   "tuning": [2, 32, 8, 1, 1024, 0xFFFFFFFF, 2],
+                   "digest": "29266d046d1222ae", "fetch_kib": 98394.6, "write_kib": 335977.1,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 PROFILE_EVERY = 8  # frames per profiled frame in the timed loop
@@ -78,6 +80,33 @@ def cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def host_info() -> dict:
+    """The host the line was measured on: cores this process may use, the
+    machine's logical CPUs, and the CPU model."""
+    return {"cores_available": len(os.sched_getaffinity(0)), "logical_cpus": os.cpu_count(),
+            "cpu_model": cpu_model()}
+
+
+MIN_P99_SAMPLES = 100
+
+
+LATENCY_FRAMES = 1000
+
+
+def latency_fields(spans_ms, source: str = "timed frames") -> dict:
+    """p50 / p99 of per-frame spans, one per frame; p99 is null with fewer
+    than MIN_P99_SAMPLES frames, where it would be little more than the
+    largest sample."""
+    spans = np.asarray(spans_ms, dtype=np.float64)
+    return {"p50_frame_ms": float(np.percentile(spans, 50)) if spans.size else None,
+            "p99_frame_ms": (float(np.percentile(spans, 99)) if spans.size >= MIN_P99_SAMPLES
+                             else None),
+            "max_frame_ms": float(spans.max()) if spans.size else None,
+            "latency_samples": int(spans.size),
+            "latency_source": f"{source}: HIP events on the frame stream before every frame "
+                              f"and after the last"}
 
 
 def make_points(n: int, dist: str) -> np.ndarray:
@@ -117,7 +146,7 @@ def cpu_baseline(n, w, h, frames, dist="uniform", footprint=1):
     dt = time.perf_counter() - t0
     what = "full frames" if m == n else f"frames of the first 2^24 of the 2^{int(np.log2(n))} points"
     return {"value": m * frames / dt / 1e9, "unit": "Gpoints/s", "cores": 1, "kind": "oracle",
-            "cpu": cpu_model(),
+            "cpu": cpu_model(), "host_cores_available": len(os.sched_getaffinity(0)),
             "sample": f"{frames} {what} ({dist}, {w}x{h}, footprint {footprint}), "
                       f"{dt:.1f} s on one host core",
             "ms_per_frame": dt / frames * 1e3}
@@ -257,8 +286,10 @@ def bench_batched(args) -> dict:
     for a in allocs:
         mm.mm_free(a)
     mm.mm_destroy_instance(inst)
+    # the frame's byte model: positions read and written, and per pixel a key
+    # clear, a key read and an RGBA8 write (as for the plain frame)
     point_bytes = POINT_BYTES * total_pts
-    batch_bytes = point_bytes + 4 * total_px
+    batch_bytes = point_bytes + PIXEL_BYTES * total_px
     return {
         "metric": "batched displace+render Gpoints/s & frames/s, 64 clouds (2^12..2^22 pts), "
                   "1-4 views each; vs plain launches",
@@ -274,15 +305,18 @@ def bench_batched(args) -> dict:
                    "splits": tuning[2], "grid_blocks": tuning[3], "bin_threads": tuning[4]},
         "frames_per_s": K / t_batch,
         "views_per_s": K * len(views) / t_batch,
-        "p50_frame_ms": float(np.percentile(frame_ms, 50)),
-        "p99_frame_ms": float(np.percentile(frame_ms, 99)),
+        **{k: v for k, v in latency_fields(frame_ms).items() if k != "latency_source"},
+        "latency_source": "HIP events before each batch frame's upload and after its graph "
+                          "(every timed frame)",
         "plain": {"value": total_pts * K / t_plain / 1e9, "unit": "Gpoints/s",
                   "ms_per_step": t_plain / K * 1e3, "frames_per_s": K / t_plain,
                   "launches_per_frame": len(views)},
         "speedup_vs_plain": t_plain / t_batch,
         "frame_roofline": {"bytes_per_frame": batch_bytes,
+                           "byte_model": "24 B per point + 20 B per pixel",
                            "achieved_GBps": batch_bytes / (t_batch / K) / 1e9,
                            "frac": batch_bytes / (t_batch / K) / 1e9 / HBM_PEAK_GBS},
+        "host": host_info(),
     }
 
 
@@ -618,6 +652,8 @@ def main() -> int:
     ap.add_argument("--bin-threads", type=int, default=0, help="threads per bin workgroup")
     ap.add_argument("--piece-records", type=int, default=0,
                     help="frame: records per balanced tile piece (0 auto or -1: static splits)")
+    ap.add_argument("--cull", choices=["auto", "on", "off"], default="auto",
+                    help="frame: the occlusion cull of the binned 3D 1x1 pass (auto: where it applies)")
     ap.add_argument("--autotune", action="store_true", help="time the shapes, keep the fastest")
     ap.add_argument("--palette", action="store_true",
                     help="frame: colour through a 256-entry palette and 1-byte indices (mm_set_colour)")
@@ -700,9 +736,11 @@ def main() -> int:
     if args.autotune:
         mm.mm_autotune(view, 10)
     elif (splat != mm.MM_SPLAT_AUTO or args.tile or args.ppt or args.splits or args.bin_threads
-          or args.piece_records):
+          or args.piece_records or args.cull != "auto"):
         pieces = mm.MM_PIECES_STATIC if args.piece_records < 0 else args.piece_records
-        mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits, args.bin_threads, pieces)
+        cull = {"auto": mm.MM_CULL_AUTO, "on": mm.MM_CULL_ON, "off": mm.MM_CULL_OFF}[args.cull]
+        mm.mm_set_tuning(view, splat, args.tile, args.ppt, args.splits, args.bin_threads, pieces,
+                         cull)
     tuning = mm.mm_get_tuning(view)
     mode = "direct" if tuning[0] == mm.MM_SPLAT_DIRECT else "binned"
     if args.palette:
@@ -732,17 +770,40 @@ def main() -> int:
     cam_arrs = [np.ascontiguousarray(cams[W + k], dtype=np.float32).reshape(16) for k in range(K)]
     cam_ptrs = [mm._fptr(a) for a in cam_arrs]  # cam_arrs keeps the memory alive
     mm.mm_profile_begin(view, prof_cap)  # synchronises
+    # one event before every frame and one after the last (outside the frame
+    # graph): the per-frame spans for p50 / p99
+    mm.mm_mark_begin(view, K + 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
         st = L.mm_set_camera(view, cam_ptrs[k]) or L.mm_step_render(view, W + k)
         if st:
             raise mm.MMError(st, "frame loop", mm.mm_last_error())
-    mm.mm_flush_frame(view)  # with overlap, the last frame is drawn inside the timed region
+    # with overlap, the last frame is drawn inside the timed region; the
+    # closing mark follows it
+    mm.mm_mark_end(view)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    frame_spans = mm.mm_mark_read(view, K + 1)
     splat_ms, resolve_ms, frame_ms = mm.mm_profile_end(view, prof_cap)
     elapsed = t1 - t0
+    # p99 from fewer than MIN_P99_SAMPLES frames is little more than the
+    # largest one: then a latency run of LATENCY_FRAMES further frames of the
+    # same loop (after the timed region) gives the distribution
+    lat_spans, lat_source = frame_spans, "timed frames"
+    if K < MIN_P99_SAMPLES:
+        R = LATENCY_FRAMES
+        lat_cams = [np.ascontiguousarray(frame_camera(args.dist, W + K + k, w, h),
+                                         dtype=np.float32).reshape(16) for k in range(R)]
+        lat_ptrs = [mm._fptr(a) for a in lat_cams]
+        mm.mm_mark_begin(view, R + 1)
+        for k in range(R):
+            st = L.mm_set_camera(view, lat_ptrs[k]) or L.mm_step_render(view, W + K + k)
+            if st:
+                raise mm.MMError(st, "latency loop", mm.mm_last_error())
+        mm.mm_mark_end(view)
+        lat_spans = mm.mm_mark_read(view, R + 1)
+        lat_source = f"a latency run of {R} frames after the {K} timed ones"
     mm.mm_destroy_view(view)
     mm.mm_free(alloc)
     mm.mm_destroy_instance(inst)
@@ -774,11 +835,14 @@ def main() -> int:
                              if args.overlap else "one hipGraph per frame"),
                    "colour": "256-entry palette, 1-byte indices" if args.palette else "index hash",
                    "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2],
-                   "splits": tuning[3], "bin_threads": tuning[4], "piece_records": tuning[5]},
+                   "splits": tuning[3], "bin_threads": tuning[4], "piece_records": tuning[5],
+                   "occlusion_cull": "on" if tuning[6] == mm.MM_CULL_ON else "off"},
         "frames_per_s": K / elapsed,
-        "p50_frame_ms": float(np.percentile(frame_ms, 50)),
-        "p99_frame_ms": float(np.percentile(frame_ms, 99)),
-        "profiled_frames": f"{len(frame_ms)} (1 in {PROFILE_EVERY} of the timed frames)",
+        **latency_fields(lat_spans, lat_source),
+        "timed_frames_p50_ms": float(np.percentile(frame_spans, 50)),
+        "timed_frames_max_ms": float(np.max(frame_spans)),
+        "kernel_profiled_frames": f"{len(frame_ms)} (1 in {PROFILE_EVERY} of the timed frames)",
+        "graph_ms_profiled_mean": float(np.mean(frame_ms)),
         "point_kernel_ms": splat_avg,
         "rest_of_frame_ms": float(np.mean(resolve_ms)),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -792,6 +856,7 @@ def main() -> int:
                            "achieved_GBps": frame_bytes / (elapsed / K) / 1e9,
                            "frac": frame_bytes / (elapsed / K) / 1e9 / HBM_PEAK_GBS},
         "stream_copy_GBps": copy_ceiling,
+        "host": host_info(),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, w, h, args.cpu_frames, args.dist, args.footprint)

@@ -250,9 +250,24 @@ typedef struct {
                                    workgroups per tile; 0 = auto (static when
                                    splits is set or below 8192 bin workgroups,
                                    else balanced by load) */
+    uint32_t occlusion_cull;    /* binned 3D views with the 1x1 footprint, one static
+                                   split per tile and no frame overlap: MM_CULL_ON drops
+                                   the records that points of the same frame provably
+                                   hide. The points that won each pixel in the previous
+                                   frame are moved and projected as this frame's are;
+                                   a record deeper than such a point at its pixel's 8x8
+                                   block cannot win. Frames are unchanged; fewer records
+                                   are written and read. MM_CULL_OFF: every record is
+                                   kept. 0 = auto (off). With ON and bin_threads /
+                                   points_per_thread left 0, a bin workgroup is 512
+                                   threads of 16 points. mm_get_tuning reports ON or
+                                   OFF. */
 } mm_tuning;
 
 #define MM_PIECES_STATIC 0xFFFFFFFFu
+#define MM_CULL_AUTO 0u
+#define MM_CULL_ON 1u
+#define MM_CULL_OFF 2u
 
 /* Chooses the splat strategy and its shape for later frames; reallocates the
  * view's scratch buffers and rebuilds its graph. Synchronises. Returns
@@ -296,6 +311,22 @@ mm_status mm_profile_begin(mm_view view, uint32_t capacity);
 mm_status mm_profile_every(mm_view view, uint32_t every);
 mm_status mm_profile_end(mm_view view, float* splat_ms, float* resolve_ms, float* frame_ms,
                          uint32_t* count);
+
+/* Frame marks, for the latency of every frame of a loop: from
+ * mm_mark_begin on, each of the next `capacity` calls of mm_step_render
+ * records one HIP event on the instance's stream just before it enqueues its
+ * frame (outside the frame graph, so every frame launches the same graph).
+ * mm_mark_end stops marking; if marks are left it records one more after
+ * the last frame (drawing a pending overlapped frame first). It does not
+ * wait. mm_mark_read waits for the last mark and writes to interval_ms (an
+ * array of `capacity` - 1; may be NULL) the time between consecutive marks:
+ * frame k's span on the device, from the point its stream reached frame k
+ * to the point it reached the next mark, idle gaps included, and to *count
+ * the number of intervals. A loop of K frames takes capacity K + 1.
+ * 2 <= capacity <= 2^20. */
+mm_status mm_mark_begin(mm_view view, uint32_t capacity);
+mm_status mm_mark_end(mm_view view);
+mm_status mm_mark_read(mm_view view, float* interval_ms, uint32_t* count);
 
 /* ------------------------------------------------------- structured grids
  * The paper's voxel view of a 2D structured domain (section "Potts model":
@@ -480,7 +511,15 @@ mm_status mm_batch_profile_end(mm_batch batch, float* frame_ms, uint32_t* count)
  * request. It is held from admission until the session is closed, or until
  * the scheduler evicts it (least recently used first) while it is idle and
  * the budget is needed by a waiting session; an evicted session's frame is
- * lost. The server's calls may come from any thread. */
+ * lost. A session evicted with requests still queued is admitted again
+ * when its next request's turn comes.
+ *
+ * Failure: if a launch fails (or cannot be sent), or a frame buffer within
+ * the budget cannot be allocated even after every other one is given up,
+ * the server stops scheduling: that launch's requests and every queued one
+ * are dropped (mm_server_poll and mm_server_wait return an error for them,
+ * stats.dropped counts them) and later submissions fail with MM_ERR_HIP.
+ * The server's calls may come from any thread. */
 typedef struct {
     uint64_t fb_budget_bytes;   /* frame-buffer bytes the admitted sessions may hold */
     uint32_t streams;           /* launches in flight at once: 1..4 */
@@ -492,11 +531,16 @@ typedef struct {
 } mm_server_desc;
 
 typedef struct {
-    uint64_t submitted, completed, launches;
+    uint64_t submitted;
+    uint64_t completed;          /* requests whose frame is complete */
+    uint64_t launches;
     uint64_t admitted_sessions;  /* sessions holding a frame buffer now */
     uint64_t admissions, evictions;
     uint64_t fb_bytes_in_use;    /* held by admitted sessions and kept for reuse */
     uint64_t queued;             /* submitted, not yet launched */
+    uint64_t dropped;            /* requests that will not complete (failure, shutdown) */
+    uint64_t max_in_flight;      /* most launches sent and not yet retired at one time */
+    uint64_t max_batch;          /* most requests in one launch */
 } mm_server_stats;
 
 /* Creates the server and starts its scheduler thread. Its streams are
@@ -525,7 +569,8 @@ mm_status mm_server_submit(mm_server server, uint32_t session, uint32_t cloud,
 mm_status mm_server_poll(mm_server server, uint64_t request_id, int32_t* done,
                          double* latency_s);
 
-/* Blocks until the request is complete (or the server stops: MM_ERR_NOT_READY). */
+/* Blocks until the request is complete. MM_ERR_NOT_READY if it will not
+ * complete: the server stopped, or failed (see below). */
 mm_status mm_server_wait(mm_server server, uint64_t request_id, double* latency_s);
 
 /* Copies the session's frame (its last completed request drawn into it) to

@@ -36,6 +36,7 @@ MM_SPLAT_AUTO = 0
 MM_SPLAT_DIRECT = 1
 MM_SPLAT_BINNED = 2
 MM_PIECES_STATIC = 0xFFFFFFFF
+MM_CULL_AUTO, MM_CULL_ON, MM_CULL_OFF = 0, 1, 2
 MM_DOMAIN_2D = 2
 MM_DOMAIN_3D = 3
 
@@ -69,7 +70,7 @@ class mm_view_desc(C.Structure):
 class mm_tuning(C.Structure):
     _fields_ = [("splat", C.c_uint32), ("tile", C.c_uint32), ("points_per_thread", C.c_uint32),
                 ("splits", C.c_uint32), ("bin_threads", C.c_uint32),
-                ("piece_records", C.c_uint32)]
+                ("piece_records", C.c_uint32), ("occlusion_cull", C.c_uint32)]
 
 
 class mm_colour_desc(C.Structure):
@@ -156,7 +157,8 @@ class mm_server_desc(C.Structure):
 class mm_server_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "launches",
                                            "admitted_sessions", "admissions", "evictions",
-                                           "fb_bytes_in_use", "queued")]
+                                           "fb_bytes_in_use", "queued", "dropped",
+                                           "max_in_flight", "max_batch")]
 
 
 _lib = None
@@ -201,6 +203,9 @@ def _declare(L):
         "mm_get_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
         "mm_profile_begin": ([_vp, C.c_uint32], _status),
         "mm_profile_every": ([_vp, C.c_uint32], _status),
+        "mm_mark_begin": ([_vp, C.c_uint32], _status),
+        "mm_mark_end": ([_vp], _status),
+        "mm_mark_read": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
         "mm_prepare_views": ([_vp, _vp], _status),
         "mm_update_views": ([_vp, _vp], _status),
         "mm_profile_end": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_float),
@@ -350,23 +355,30 @@ def mm_destroy_view(view: int) -> None:
 
 def mm_set_tuning(view: int, splat: int = MM_SPLAT_AUTO, tile: int = 0,
                   points_per_thread: int = 0, splits: int = 0, bin_threads: int = 0,
-                  piece_records: int = 0) -> None:
-    t = mm_tuning(splat, tile, points_per_thread, splits, bin_threads, piece_records)
+                  piece_records: int = 0, occlusion_cull: int = 0) -> None:
+    t = mm_tuning(splat, tile, points_per_thread, splits, bin_threads, piece_records,
+                  occlusion_cull)
     _check(lib().mm_set_tuning(view, C.byref(t)), "mm_set_tuning")
 
 
-def mm_get_tuning(view: int) -> tuple[int, int, int, int, int, int]:
-    """(splat, tile, points_per_thread, splits, bin_threads, piece_records) in use."""
+def _tuning_tuple(t: mm_tuning) -> tuple:
+    return (t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads, t.piece_records,
+            t.occlusion_cull)
+
+
+def mm_get_tuning(view: int) -> tuple[int, int, int, int, int, int, int]:
+    """(splat, tile, points_per_thread, splits, bin_threads, piece_records,
+    occlusion_cull) in use."""
     t = mm_tuning()
     _check(lib().mm_get_tuning(view, C.byref(t)), "mm_get_tuning")
-    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads, t.piece_records
+    return _tuning_tuple(t)
 
 
-def mm_autotune(view: int, frames: int = 10) -> tuple[int, int, int, int, int, int]:
+def mm_autotune(view: int, frames: int = 10) -> tuple[int, int, int, int, int, int, int]:
     """Times the supported shapes, keeps the fastest; returns it as mm_get_tuning does."""
     t = mm_tuning()
     _check(lib().mm_autotune(view, frames, C.byref(t)), "mm_autotune")
-    return t.splat, t.tile, t.points_per_thread, t.splits, t.bin_threads, t.piece_records
+    return _tuning_tuple(t)
 
 
 def mm_set_camera(view: int, view_proj) -> None:
@@ -508,6 +520,23 @@ def mm_profile_end(view: int, capacity: int):
            "mm_profile_end")
     k = n.value
     return s[:k], r[:k], f[:k]
+
+
+def mm_mark_begin(view: int, capacity: int) -> None:
+    _check(lib().mm_mark_begin(view, capacity), "mm_mark_begin")
+
+
+def mm_mark_end(view: int) -> None:
+    _check(lib().mm_mark_end(view), "mm_mark_end")
+
+
+def mm_mark_read(view: int, capacity: int) -> np.ndarray:
+    """Intervals (ms) between consecutive frame marks: one per marked frame
+    (a loop of K frames takes capacity K + 1)."""
+    out = np.zeros(max(1, capacity - 1), dtype=np.float32)
+    n = C.c_uint32()
+    _check(lib().mm_mark_read(view, _fptr(out), C.byref(n)), "mm_mark_read")
+    return out[:n.value]
 
 
 # ------------------------------------------------------------------- batches

@@ -665,7 +665,7 @@ mm_status mm_batch_autotune(mm_batch b, uint32_t frames, mm_batch_tuning* out) {
     if (best_ms == 0.0f) return fail(MM_ERR_HIP, "batch_autotune: no candidate ran");
     MM_TRY(mm_batch_set_tuning(b, &best));
     const uint32_t vals[kTuneValues] = {best.tile, best.points_per_thread, best.splits,
-                                        best.grid_blocks, best.bin_threads, 0u};
+                                        best.grid_blocks, best.bin_threads, 0u, 0u};
     tune_cache_store(key, vals);
     return mm_batch_get_tuning(b, out);
 }

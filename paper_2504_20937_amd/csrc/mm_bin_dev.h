@@ -94,18 +94,132 @@ __device__ __forceinline__ void displace_cloud(const CloudArgs& c, uint32_t i, f
     store_point<DIM>(c.pos, i, x, y, z);
 }
 
+// The tile holding stage record j: the number of tiles whose run ends at or
+// before j (hist[b] = end of tile b's run, non-decreasing), found with a
+// fixed 12-step branch-free search, so a thread's searches for its PPT
+// records interleave.
+__device__ __forceinline__ uint32_t tile_of_record(const uint32_t* hist, uint32_t nt, uint32_t j) {
+    static_assert(kMaxPlanTiles == 4096, "12 steps cover 4096 tiles");
+    uint32_t b = 0;
+#pragma unroll
+    for (uint32_t step = 2048; step != 0; step >>= 1) {
+        const uint32_t c = b + step;
+        if (c <= nt && hist[c - 1] <= j) b = c;
+    }
+    return b;
+}
+
+// Survivors before stage position j, from the windows' keep masks and
+// exclusive bases (window w = records 64 w .. 64 w + 63).
+__device__ __forceinline__ uint32_t kept_before(const uint64_t* mask, const uint32_t* base,
+                                                uint32_t j) {
+    const uint32_t w = j >> 6, bit = j & 63u;
+    const uint64_t below = bit ? (mask[w] & (~0ull >> (64u - bit))) : 0ull;
+    return base[w] + static_cast<uint32_t>(__popcll(below));
+}
+
+// The culled write of a chunk sorted by tile in the stage (hist[b] = end of
+// tile b's run, hist[nt] = total): every thread takes its records j = tid,
+// tid + NT, ... (consecutive lanes, consecutive records), finds each one's
+// tile, reads the tile's cull record (bitmap word of the pixel and bound of
+// its 8x8 block, all loads in flight together; neighbouring lanes mostly
+// share a tile, so a wave touches few cache lines), and keeps the record
+// unless its pixel is covered and its depth exceeds the bound. Survivors keep
+// their stage order: a record's output position is the number of survivors
+// before it (per-window ballots and a scan of the window counts), so each
+// tile's survivors form one run and the table row holds the surviving starts.
+// Tiles are stamped from the counts before the cull: a tile's winner is never
+// ruled out, so a tile with points keeps a survivor in some chunk.
+// post() runs once the cull-record loads are issued (the kernel's deferred
+// position stores).
+// LDS beside the stage and histogram: mask (P / 64 u64) and base (P / 64 + 1 u32).
+template <int PPT, uint32_t NT, typename Post>
+__device__ __forceinline__ void cull_write(const BinView& v, uint32_t chunk, uint32_t shift,
+                                           uint32_t stamp, const uint64_t* stage,
+                                           const uint32_t* hist, uint64_t* mask, uint32_t* base,
+                                           Post post) {
+    constexpr uint32_t P = NT * PPT, NW = NT / 64, NWIN = P / 64;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    const uint32_t nt = v.ntiles, total = hist[nt];
+    const uint32_t side = 1u << shift, words = cull_words(side), bmw = cull_bitmap_words(side);
+    const uint32_t blk_shift = shift - 3u;
+    // every record's two cull-record words are loaded first (all in flight
+    // together; a record is read again from LDS where it is needed, so only
+    // the loaded words stay in registers), then post() issues the deferred
+    // stores, then the words are used
+    uint32_t word[PPT], bound[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint32_t j = static_cast<uint32_t>(k) * NT + tid;
+        const uint64_t r = j < total ? stage[j] : 0ull;
+        // past the chunk's records: any tile (the record is not kept)
+        const uint32_t tb = min(tile_of_record(hist, nt, j), nt - 1u);
+        const uint32_t q = (static_cast<uint32_t>(r) & 0xFFFFu) >> 3;
+        const uint32_t blk = (((q >> shift) >> 3) << blk_shift) | ((q & (side - 1u)) >> 3);
+        const uint32_t* rec = v.cull + static_cast<uint64_t>(tb) * words;
+        word[k] = rec[q >> 5];
+        bound[k] = rec[bmw + blk];
+    }
+    post();
+    uint32_t keep = 0;  // bit k: record k of this thread survives
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint32_t j = static_cast<uint32_t>(k) * NT + tid;
+        const uint64_t r = j < total ? stage[j] : 0ull;
+        const uint32_t q = (static_cast<uint32_t>(r) & 0xFFFFu) >> 3;
+        const bool covered = ((word[k] >> (q & 31u)) & 1u) != 0u;
+        const bool kp = j < total && !(covered && static_cast<uint32_t>(r >> 32) > bound[k]);
+        keep |= (kp ? 1u : 0u) << k;
+        const uint64_t m = __ballot(kp);
+        if (lane == 0) mask[static_cast<uint32_t>(k) * NW + wave] = m;
+    }
+    __syncthreads();
+    if (wave == 0) {  // exclusive scan of the windows' counts
+        uint32_t carry = 0;
+        for (uint32_t w0 = 0; w0 < NWIN; w0 += 64u) {
+            const uint32_t w = w0 + lane;
+            const uint32_t c = w < NWIN ? static_cast<uint32_t>(__popcll(mask[w])) : 0u;
+            const uint32_t inc = wave_inclusive_scan(c, lane);
+            if (w < NWIN) base[w] = carry + inc - c;
+            carry += __shfl(inc, 63, 64);
+        }
+        if (lane == 0) base[NWIN] = carry;
+    }
+    __syncthreads();
+    uint64_t* seg = v.seg + static_cast<uint64_t>(chunk) * P;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const uint32_t j = static_cast<uint32_t>(k) * NT + tid;
+        if ((keep >> k) & 1u) seg[kept_before(mask, base, j)] = stage[j];
+    }
+    uint16_t* row = v.table + static_cast<uint64_t>(chunk) * (nt + 1u);
+    for (uint32_t b = tid; b <= nt; b += NT) {
+        const uint32_t s = b == 0 ? 0u : hist[b - 1];
+        row[b] = static_cast<uint16_t>(s >= P ? base[NWIN] : kept_before(mask, base, s));
+    }
+    for (uint32_t b = tid; b < nt; b += NT) {
+        const uint32_t s = b == 0 ? 0u : hist[b - 1];
+        if (hist[b] > s) store_flag(&v.active[b], stamp);
+    }
+}
+
 // Bin one chunk of points into the tiles of one view: segment `chunk` of
 // v.seg, row `chunk` of v.table, and the stamps of the tiles that received
 // points. pre(i, x, y, z) runs on each point before its projection, in the
 // same loop (the displacement: its stores then drain under the projection
 // and histogram work). On entry hist[0..ntiles] is zero and visible to the
-// whole block.
-template <int DIM, int PPT, uint32_t NT, typename Pre>
+// whole block. With CULL the records the view's cull records rule out are
+// not written (see cull_write); the table then holds the surviving runs.
+struct NoOp {
+    __device__ void operator()() const {}
+};
+
+template <int DIM, int PPT, uint32_t NT, typename Pre, bool CULL = false, typename Post = NoOp>
 __device__ __forceinline__ void bin_view(const BinView& v, uint32_t n, uint32_t chunk,
                                          uint32_t base, uint32_t shift, uint32_t stamp,
                                          float (&xs)[PPT], float (&ys)[PPT], float (&zs)[PPT],
                                          uint64_t* stage, uint32_t* hist, uint32_t* wave_sum,
-                                         Pre pre) {
+                                         Pre pre, Post post = Post{}) {
     constexpr uint32_t P = NT * PPT;
     const uint32_t tid = threadIdx.x;
     const uint32_t nt = v.ntiles;
@@ -144,6 +258,15 @@ __device__ __forceinline__ void bin_view(const BinView& v, uint32_t n, uint32_t 
     }
     __syncthreads();
 
+    if constexpr (CULL) {
+        if (v.cull) {
+            __shared__ uint64_t cull_mask[P / 64];
+            __shared__ uint32_t cull_base[P / 64 + 1];
+            cull_write<PPT, NT>(v, chunk, shift, stamp, stage, hist, cull_mask, cull_base, post);
+            return;
+        }
+        post();
+    }
     // hist[b] is now the end of bin b (= start of bin b + 1); hist[nt] the total
     const uint32_t total = hist[nt];
     uint64_t* seg = v.seg + static_cast<uint64_t>(chunk) * P;

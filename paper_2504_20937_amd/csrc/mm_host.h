@@ -157,9 +157,9 @@ mm_status validate_camera(const float m[16], const char* what);
 namespace mmh {
 
 // Autotuning cache: a text file named by the environment variable
-// MM_TUNE_CACHE, one "key v0 .. v5" line per tuned shape; later lines win.
+// MM_TUNE_CACHE, one "key v0 .. v6" line per tuned shape; later lines win.
 // Without the variable nothing is read or written.
-constexpr int kTuneValues = 6;
+constexpr int kTuneValues = 7;
 bool tune_cache_lookup(const std::string& key, uint32_t out[kTuneValues]);
 void tune_cache_store(const std::string& key, const uint32_t v[kTuneValues]);
 // gcnArchName of a device (e.g. "gfx950:sramecc+:xnack-"), "" on failure.

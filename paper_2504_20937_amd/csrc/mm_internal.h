@@ -57,6 +57,30 @@ struct ResolveArgs {
     Palette pal;
 };
 
+// Occlusion cull of a binned view (3D, 1x1 footprint, one tile-pass
+// workgroup per tile). Per frame the hint kernel takes the winning point of
+// every pixel of the previous frame (the hints), moves it by this frame's
+// step and projects it with this frame's camera, and writes one cull record
+// per screen tile. A pixel is covered when such a point lands on it; no point
+// landing there can then win with a larger depth than that point's. The bin
+// kernel drops a record whose pixel is covered and whose depth exceeds the
+// bound of its 8x8-pixel block (the largest of the block's covered pixels'
+// depths), so the dropped record loses its pixel to a point of this frame:
+// the frame is unchanged, only fewer records are written and read.
+//
+// A cull record of a tile of side S (cull_words(S) u32): the covered bitmap
+// (S*S/32 words, bit q of the tile's pixels in row-major order), then the
+// bound of each 8x8 block ((S/8)^2 words, depth bits), padded to 16 words.
+// The hint kernel merges into the records with atomic OR and MAX, so every
+// record is zero before it runs: the one-split 1x1 tile pass zeroes each
+// tile's record after the bin pass has read it.
+__host__ __device__ constexpr uint32_t cull_bitmap_words(uint32_t side) { return side * side / 32u; }
+__host__ __device__ constexpr uint32_t cull_blocks(uint32_t side) { return (side / 8u) * (side / 8u); }
+__host__ __device__ constexpr uint32_t cull_words(uint32_t side) {
+    return (cull_bitmap_words(side) + cull_blocks(side) + 15u) / 16u * 16u;
+}
+constexpr uint32_t kNoHint = 0xFFFFFFFFu;
+
 // Binned splat, bin pass side of one view.
 struct BinView {
     ViewGeom g;
@@ -64,6 +88,9 @@ struct BinView {
     uint16_t* table;     // num_wg rows of ntiles + 1 tile start offsets
     uint32_t* active;    // ntiles: stamp of the last frame the tile received points
     uint32_t tiles_x, ntiles;
+    uint32_t* cull;        // occlusion cull: ntiles records (nullptr: no cull)
+    const uint32_t* hint;  // occlusion cull: ntiles * S * S point indices, tile-major
+                           // (pixel q = y * S + x of tile t at t * S * S + q), kNoHint = none
 };
 
 // Binned splat, tile and merge side of one view.
@@ -89,6 +116,10 @@ struct TileView {
                          // holds no earlier frame); 0: only tiles drawn last frame
     uint32_t seed_lo, seed_hi;
     Palette pal;
+    uint32_t* hint;      // occlusion cull: the one-split 1x1 pass writes each drawn
+                         // tile's winning point indices here (nullptr: none)
+    uint32_t* cull;      // occlusion cull: the one-split 1x1 pass zeroes each tile's
+                         // cull record (nullptr: none)
 };
 
 // Binned splat of one cloud into one view.
@@ -164,6 +195,12 @@ hipError_t launch_fill(uint64_t* keys, uint64_t nkeys, uint64_t value, hipStream
 // stream order: no switch to a copy engine between the kernels around it.
 hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+// Bin workgroup shapes that have a culled bin kernel: 1024 threads of 16
+// points would need more registers than four waves per SIMD allow.
+__host__ __device__ constexpr bool cull_shape_ok(int ppt, uint32_t threads) {
+    return !(ppt == 16 && threads == 1024);
+}
+
 // Binned splat. Tile side 1 << shift with shift in {4, 5, 6}; bin workgroups
 // of `threads` in {256, 512, 1024} threads with points per thread in
 // {4, 8, 16} (chunk P = threads * ppt points); splits per tile in
@@ -171,12 +208,16 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
 constexpr uint32_t kMaxLdsBytes = 163840;  // per workgroup on gfx950
 bool binned_shape_ok(int shift, int ppt, uint32_t threads, uint32_t splits);
 size_t bin_lds_bytes(int ppt, uint32_t threads, uint32_t ntiles);
+// cull: the kernel reads the view's cull records (3D only).
 Launch bin_launch(int dim, bool wrap, Phase phase, int ppt, uint32_t threads, uint32_t n,
-                  uint32_t ntiles);
+                  uint32_t ntiles, bool cull = false);
 Launch tile_launch(int footprint, int shift, uint32_t ntiles, uint32_t splits);
 Launch merge_launch(int footprint, int shift, uint32_t ntiles);
 // 1x1 footprint, one split: the tile pass resolves to RGBA8 itself (no merge).
 Launch tile_fused_launch(int shift, uint32_t ntiles);
+// Occlusion cull records of a 3D view for this frame (BinArgs of the frame:
+// step, camera, stamp); the bin kernel of the frame follows it.
+Launch hint_launch(int shift, bool wrap, uint32_t ntiles);
 Launch seam_launch(int shift, uint32_t ntiles);
 // Load-balanced tile pass: the table made tile-major with the tiles' record
 // totals, the plan, then a persistent grid of tile workgroups over the work

@@ -23,11 +23,16 @@
 
 namespace {
 
+// Events of a timed frame graph: before the first node, before the point
+// pass (after the occlusion hint kernel, if any), after the point pass, and
+// after the last node.
+constexpr int kFrameEvents = 4;
+
 struct FrameGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t first = nullptr;                 // node whose arguments change per frame
-    hipGraphNode_t ev[3] = {nullptr, nullptr, nullptr};
+    hipGraphNode_t per_frame[2] = {nullptr, nullptr};  // nodes whose arguments change per frame
+    hipGraphNode_t ev[kFrameEvents] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -52,6 +57,9 @@ struct mm_view_s {
     uint64_t* part = nullptr;
     uint64_t* border = nullptr;
     uint64_t* apron = nullptr;
+    // occlusion cull: per-tile cull records and last frame's winner per pixel
+    uint32_t* cull = nullptr;
+    uint32_t* hint = nullptr;
     // load-balanced tile pass
     uint32_t* col_sum = nullptr;
     uint16_t* tcol = nullptr;
@@ -64,12 +72,20 @@ struct mm_view_s {
     mm::ResolveArgs rargs{};
     mm::BinArgs bargs{};
     mm::TileArgs targs{};
-    std::vector<mm::Launch> nodes;  // frame graph kernels in order; [0] takes per-frame args
+    // frame graph kernels in order; the first frame_nodes take the per-frame
+    // arguments (the occlusion hint kernel, if any, then the point pass), the
+    // rest are the tile passes
+    std::vector<mm::Launch> nodes;
+    uint32_t frame_nodes = 1;
     FrameGraph plain, timed;
-    std::vector<hipEvent_t> events;  // 3 per profiled frame
+    std::vector<hipEvent_t> events;  // kFrameEvents per profiled frame
     uint32_t prof_cap = 0, prof_count = 0;
     uint32_t prof_every = 1, prof_skip = 0;  // record 1 frame in prof_every
     bool profiling = false;
+    // frame marks: one event before each frame, one after the last
+    std::vector<hipEvent_t> marks;
+    uint32_t mark_cap = 0, mark_count = 0;
+    bool marking = false;
     // Frame overlap (binned only): frame f is binned into record set f & 1 on
     // the instance stream while frame f - 1 is drawn from the other set on
     // the render stream. Set 1 mirrors seg / table / active.
@@ -104,7 +120,7 @@ bool binned(mm_view v) { return v->tuning.splat == MM_SPLAT_BINNED; }
 
 // Argument block of frame-graph node k.
 void* node_arg(mm_view v, size_t k) {
-    if (binned(v)) return k == 0 ? static_cast<void*>(&v->bargs) : static_cast<void*>(&v->targs);
+    if (binned(v)) return k < v->frame_nodes ? static_cast<void*>(&v->bargs) : static_cast<void*>(&v->targs);
     return k == 0 ? static_cast<void*>(&v->args) : static_cast<void*>(&v->rargs);
 }
 
@@ -115,7 +131,8 @@ void destroy_graph(FrameGraph& fg) {
 }
 
 // The frame graph: the kernels of v->nodes in a chain; with timed set,
-// event-record nodes go before the first kernel, after it, and at the end.
+// event-record nodes go before the first kernel, before and after the point
+// pass, and at the end.
 mm_status build_graph(mm_view v, bool timed, FrameGraph& out) {
     FrameGraph fg;
     MM_HIP(hipGraphCreate(&fg.graph, 0));
@@ -127,17 +144,19 @@ mm_status build_graph(mm_view v, bool timed, FrameGraph& out) {
                                          v->events[j]);
         prev = fg.ev[j];
     };
+    const size_t point = v->frame_nodes - 1;  // the point pass
     if (timed) add_event(0);
     for (size_t k = 0; k < v->nodes.size() && err == hipSuccess; ++k) {
+        if (timed && k == point) add_event(1);
         void* args[] = {node_arg(v, k)};
         hipKernelNodeParams p = node_params(v->nodes[k], args);
         hipGraphNode_t n = nullptr;
         err = hipGraphAddKernelNode(&n, fg.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
-        if (k == 0) fg.first = n;
+        if (k < v->frame_nodes) fg.per_frame[k] = n;
         prev = n;
-        if (timed && k == 0) add_event(1);
+        if (timed && k == point) add_event(2);
     }
-    if (timed) add_event(2);
+    if (timed) add_event(3);
     if (err == hipSuccess) err = hipGraphInstantiate(&fg.exec, fg.graph, nullptr, nullptr, 0);
     if (err != hipSuccess) {
         destroy_graph(fg);
@@ -157,8 +176,11 @@ void free_splat_buffers(mm_view v) {
                     static_cast<void*>(v->counters)})
         if (p) (void)hipFree(p);
     for (void* p : {static_cast<void*>(v->seg1), static_cast<void*>(v->table1),
-                    static_cast<void*>(v->active1)})
+                    static_cast<void*>(v->active1), static_cast<void*>(v->cull),
+                    static_cast<void*>(v->hint)})
         if (p) (void)hipFree(p);
+    v->cull = nullptr;
+    v->hint = nullptr;
     v->seg1 = nullptr;
     v->table1 = nullptr;
     v->active1 = nullptr;
@@ -195,17 +217,29 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
         else
             out.splat = (tiles(64) <= 4096u) ? MM_SPLAT_BINNED : MM_SPLAT_DIRECT;
     }
+    if (out.occlusion_cull > MM_CULL_OFF)
+        return fail(MM_ERR_INVALID_ARG, "tuning: occlusion_cull %u unknown", out.occlusion_cull);
     if (out.splat == MM_SPLAT_DIRECT) {
+        if (out.occlusion_cull == MM_CULL_ON)
+            return fail(MM_ERR_UNSUPPORTED, "tuning: the occlusion cull needs the binned splat");
         out.tile = 0;
         out.points_per_thread = 0;
         out.splits = 0;
         out.bin_threads = 0;
         out.piece_records = 0;
+        out.occlusion_cull = MM_CULL_OFF;
         return MM_OK;
     }
+    // a view asking for the occlusion cull (3D, 1x1, one static split) by
+    // default bins 512 threads of 16 points: the culled bin kernel holds its
+    // points longer and keeps two workgroups per CU only in that shape
+    const bool cull_default = d.domain == MM_DOMAIN_3D && d.footprint == 1 &&
+                              out.occlusion_cull == MM_CULL_ON &&
+                              (out.splits == 0 || out.splits == 1) &&
+                              (out.piece_records == 0 || out.piece_records == MM_PIECES_STATIC);
     if (out.tile == 0) out.tile = tiles(32) <= 4096u ? 32u : 64u;
-    if (out.points_per_thread == 0) out.points_per_thread = 8;
-    if (out.bin_threads == 0) out.bin_threads = 1024;
+    if (out.points_per_thread == 0) out.points_per_thread = cull_default && out.bin_threads != 1024 ? 16 : 8;
+    if (out.bin_threads == 0) out.bin_threads = cull_default && out.points_per_thread == 16 ? 512 : 1024;
     // Auto: static splits up to 8191 bin workgroups (2^26 points at the
     // default chunk), where the balanced pass's count and plan kernels cost
     // more than the imbalance they remove; beyond, balanced pieces of about
@@ -247,10 +281,24 @@ mm_status resolve_tuning(const mm_view_desc& d, const mm_tuning& req, mm_tuning&
     if (tiles(out.tile) > kMaxTiles)
         return fail(MM_ERR_UNSUPPORTED, "tuning: %ux%u screen needs %u tiles of %u px (max %u)",
                     d.width, d.height, tiles(out.tile), out.tile, kMaxTiles);
+    // (the cull's window masks and bases: 12 bytes per 64 records)
     const size_t lds = mm::bin_lds_bytes(static_cast<int>(out.points_per_thread), out.bin_threads,
-                                         tiles(out.tile));
+                                         tiles(out.tile)) +
+                       12u * out.bin_threads * out.points_per_thread / 64u + 4u;
     if (lds + 1024 > mm::kMaxLdsBytes)
         return fail(MM_ERR_UNSUPPORTED, "tuning: a bin workgroup would need %zu bytes of LDS", lds);
+    // the cull takes 3D depths and the one-split 1x1 pass, which resolves
+    // each tile whole and writes its winners as the next frame's hints
+    const bool cullable = d.domain == MM_DOMAIN_3D && d.footprint == 1 &&
+                          out.piece_records == MM_PIECES_STATIC && out.splits == 1 &&
+                          mm::cull_shape_ok(static_cast<int>(out.points_per_thread), out.bin_threads);
+    if (out.occlusion_cull == MM_CULL_ON && !cullable)
+        return fail(MM_ERR_UNSUPPORTED,
+                    "tuning: the occlusion cull needs a 3D view, the 1x1 footprint, one static split "
+                    "and a bin shape other than 1024 threads x 16 points");
+    // auto leaves the cull off: measured on MI355X at 2^24 points, 1080p, the
+    // culled bin pass loses more time than the records it saves
+    out.occlusion_cull = cullable && out.occlusion_cull == MM_CULL_ON ? MM_CULL_ON : MM_CULL_OFF;
     return MM_OK;
 }
 
@@ -264,6 +312,7 @@ mm_status setup_splat(mm_view v) {
     const bool wrap = d.wrap != 0;
     hipError_t e = hipSuccess;
     v->nodes.clear();
+    v->frame_nodes = 1;
     if (!binned(v)) {
         e = alloc_n(&v->depth, npix);
         if (e == hipSuccess) e = mm::launch_fill(v->depth, npix, mm::kEmptyKey, inst->stream);
@@ -309,6 +358,21 @@ mm_status setup_splat(mm_view v) {
             e = alloc_n(&v->border, static_cast<uint64_t>(v->ntiles) * 4 * side);
             if (e == hipSuccess) e = alloc_n(&v->apron, static_cast<uint64_t>(v->ntiles) * (4 * side + 4));
         }
+        // not with frame overlap: the draw of frame f - 1, which writes the
+        // hints, runs beside the bin pass of frame f
+        const bool cull = v->tuning.occlusion_cull == MM_CULL_ON && !v->overlap;
+        if (e == hipSuccess && cull) {
+            // hints start empty (no bound until a frame is drawn); cull records
+            // are written by every frame's hint kernel before they are read
+            e = alloc_n(&v->cull, static_cast<uint64_t>(v->ntiles) * mm::cull_words(side));
+            if (e == hipSuccess)
+                e = hipMemsetAsync(v->cull, 0, static_cast<size_t>(v->ntiles) * mm::cull_words(side) * 4,
+                                   inst->stream);
+            if (e == hipSuccess) e = alloc_n(&v->hint, static_cast<uint64_t>(v->ntiles) * side * side);
+            if (e == hipSuccess)
+                e = hipMemsetAsync(v->hint, 0xFF, static_cast<size_t>(v->ntiles) * side * side * 4,
+                                   inst->stream);
+        }
         if (e != hipSuccess) return hip_fail(e, "binned splat buffers");
         v->stamp = 0;
         fill_point_args(v);
@@ -323,6 +387,8 @@ mm_status setup_splat(mm_view v) {
         b.stamp_out = v->active + v->ntiles;
         b.stamp = 0;
         b.shift = shift;
+        b.v.cull = v->cull;
+        b.v.hint = v->hint;
         mm::TileArgs& t = v->targs;
         t.v.seg = v->seg;
         t.v.table = v->table;
@@ -344,6 +410,8 @@ mm_status setup_splat(mm_view v) {
         t.v.seed_lo = v->args.c.seed_lo;
         t.v.seed_hi = v->args.c.seed_hi;
         t.v.pal = v->pal;
+        t.v.hint = v->hint;
+        t.v.cull = v->cull;
         t.stamp_in = v->active + v->ntiles;
         t.points_per_wg = static_cast<uint32_t>(P);
         t.col_sum = v->col_sum;
@@ -375,7 +443,10 @@ mm_status setup_splat(mm_view v) {
         }
         v->pending = -1;
         v->last_drawn = -1;
-        v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, nthreads, v->args.c.n, v->ntiles));
+        if (cull) v->nodes.push_back(mm::hint_launch(static_cast<int>(shift), wrap, v->ntiles));
+        v->frame_nodes = cull ? 2u : 1u;
+        v->nodes.push_back(mm::bin_launch(dim, wrap, mm::kDisplaceRender, ppt, nthreads, v->args.c.n,
+                                          v->ntiles, cull));
         if (balanced) {
             int cus = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, inst->device) != hipSuccess ||
@@ -407,11 +478,22 @@ void teardown_splat(mm_view v) {
     free_splat_buffers(v);
 }
 
+// Records the next frame mark on the instance stream, while marks are left.
+mm_status record_mark(mm_view v) {
+    if (!v->marking || v->mark_count >= v->mark_cap) return MM_OK;
+    MM_HIP(hipEventRecord(v->marks[v->mark_count], v->inst->stream));
+    v->mark_count++;
+    return MM_OK;
+}
+
 void destroy_view_resources(mm_view v) {
     teardown_splat(v);
     destroy_overlap(v);
     for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
     v->events.clear();
+    for (hipEvent_t e : v->marks) (void)hipEventDestroy(e);
+    v->marks.clear();
+    v->marking = false;
     if (v->colour) (void)hipFree(v->colour);
     v->colour = nullptr;
 }
@@ -458,7 +540,7 @@ mm::TileArgs& set_tile(mm_view v, int k) { return k ? v->targs1 : v->targs; }
 mm_status draw_set(mm_view v, int k) {
     MM_HIP(hipStreamWaitEvent(v->rstream, v->ev_bin[k], 0));
     void* args[] = {&set_tile(v, k)};
-    for (size_t n = 1; n < v->nodes.size(); ++n)
+    for (size_t n = v->frame_nodes; n < v->nodes.size(); ++n)
         MM_HIP(hipLaunchKernel(v->nodes[n].func, v->nodes[n].grid, v->nodes[n].block, args,
                                v->nodes[n].shared, v->rstream));
     MM_HIP(hipEventRecord(v->ev_drawn[k], v->rstream));
@@ -485,6 +567,7 @@ mm_status flush_frame(mm_view v) {
 // bin kernel (instance stream) and after the draw (render stream).
 mm_status overlap_frame(mm_view v, mm::Phase phase, uint32_t step) {
     MM_TRY(next_stamp(v));
+    MM_TRY(record_mark(v));
     const int k = static_cast<int>(v->stamp & 1u);
     mm::BinArgs& b = set_bin(v, k);
     b.c.step = step;
@@ -493,17 +576,18 @@ mm_status overlap_frame(mm_view v, mm::Phase phase, uint32_t step) {
     MM_HIP(hipStreamWaitEvent(s, v->ev_drawn[k], 0));
     hipEvent_t* ev = nullptr;
     if (v->profiling && v->prof_count < v->prof_cap && v->prof_skip++ % v->prof_every == 0)
-        ev = &v->events[3ull * v->prof_count++];
+        ev = &v->events[static_cast<size_t>(kFrameEvents) * v->prof_count++];
     if (ev) MM_HIP(hipEventRecord(ev[0], s));
+    if (ev) MM_HIP(hipEventRecord(ev[1], s));
     const mm::Launch bl = mm::bin_launch(static_cast<int>(v->desc.domain), v->desc.wrap != 0, phase,
                                          static_cast<int>(v->tuning.points_per_thread),
                                          v->tuning.bin_threads, v->args.c.n, v->ntiles);
     void* args[] = {&b};
     MM_HIP(hipLaunchKernel(bl.func, bl.grid, bl.block, args, bl.shared, s));
-    if (ev) MM_HIP(hipEventRecord(ev[1], s));
+    if (ev) MM_HIP(hipEventRecord(ev[2], s));
     MM_HIP(hipEventRecord(v->ev_bin[k], s));
     if (v->pending >= 0) MM_TRY(draw_set(v, v->pending));
-    if (ev) MM_HIP(hipEventRecord(ev[2], v->pending >= 0 ? v->rstream : s));
+    if (ev) MM_HIP(hipEventRecord(ev[3], v->pending >= 0 ? v->rstream : s));
     v->pending = k;
     return MM_OK;
 }
@@ -747,7 +831,7 @@ mm_status mm_create_view(mm_instance inst, const mm_view_desc* desc, mm_view* ou
         return fail(MM_ERR_INVALID_ARG, "create_view: position is not an alloc of this instance");
     MM_TRY(validate_desc(inst, desc));
     mm_tuning tuning{};
-    MM_TRY(resolve_tuning(*desc, mm_tuning{MM_SPLAT_AUTO, 0, 0, 0, 0, 0}, tuning));
+    MM_TRY(resolve_tuning(*desc, mm_tuning{MM_SPLAT_AUTO, 0, 0, 0, 0, 0, 0}, tuning));
     DeviceGuard guard(inst->device);
     mm_view v = new (std::nothrow) mm_view_s();
     if (!v) return fail(MM_ERR_OUT_OF_MEMORY, "create_view: host allocation");
@@ -791,6 +875,8 @@ mm_status mm_set_tuning(mm_view v, const mm_tuning* req) {
     MM_TRY(resolve_tuning(v->desc, *req, t));
     if (v->overlap && t.splat != MM_SPLAT_BINNED)
         return fail(MM_ERR_UNSUPPORTED, "set_tuning: frame overlap needs the binned splat");
+    if (v->overlap && req->occlusion_cull == MM_CULL_ON)
+        return fail(MM_ERR_UNSUPPORTED, "set_tuning: the occlusion cull is off with frame overlap");
     DeviceGuard guard(v->inst->device);
     MM_TRY(flush_frame(v));
     MM_HIP(hipStreamSynchronize(v->inst->stream));
@@ -814,7 +900,7 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
                   (int)d.domain, (unsigned long long)d.element_count, d.width, d.height, d.footprint);
     uint32_t cached[kTuneValues];
     if (tune_cache_lookup(key, cached)) {
-        const mm_tuning t{cached[0], cached[1], cached[2], cached[3], cached[4], cached[5]};
+        const mm_tuning t{cached[0], cached[1], cached[2], cached[3], cached[4], cached[5], cached[6]};
         if (mm_set_tuning(v, &t) == MM_OK) return mm_get_tuning(v, out);
     }
     const size_t bytes = static_cast<size_t>(d.element_count) * 4u * static_cast<size_t>(d.format);
@@ -822,14 +908,14 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     MM_HIP(hipMalloc(&saved, bytes));
     hipError_t e = hipMemcpyAsync(saved, v->position->ptr, bytes, hipMemcpyDeviceToDevice, inst->stream);
     std::vector<mm_tuning> cands;
-    if (!v->overlap) cands.push_back({MM_SPLAT_DIRECT, 0, 0, 0, 0, 0});
+    if (!v->overlap) cands.push_back({MM_SPLAT_DIRECT, 0, 0, 0, 0, 0, 0});
     for (uint32_t tile : {32u, 64u})
         for (uint32_t threads : {256u, 1024u})
             for (uint32_t ppt : {8u, 16u}) {
                 for (uint32_t pieces : {0u, 4096u, 16384u})
-                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, 0, threads, pieces});
+                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, 0, threads, pieces, 0});
                 for (uint32_t splits : {1u, 2u})
-                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, splits, threads, MM_PIECES_STATIC});
+                    cands.push_back({MM_SPLAT_BINNED, tile, ppt, splits, threads, MM_PIECES_STATIC, 0});
             }
     mm_tuning best{};
     float best_ms = 0.0f;
@@ -858,7 +944,7 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     if (best_ms == 0.0f) return fail(MM_ERR_HIP, "autotune: no candidate ran");
     MM_TRY(mm_set_tuning(v, &best));
     const uint32_t vals[kTuneValues] = {best.splat, best.tile, best.points_per_thread, best.splits,
-                                        best.bin_threads, best.piece_records};
+                                        best.bin_threads, best.piece_records, best.occlusion_cull};
     tune_cache_store(key, vals);
     return mm_get_tuning(v, out);
 }
@@ -866,6 +952,7 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
 mm_status mm_get_tuning(mm_view v, mm_tuning* out) {
     if (!v || !out) return fail(MM_ERR_INVALID_ARG, "get_tuning: null argument");
     *out = v->tuning;
+    if (v->overlap) out->occlusion_cull = MM_CULL_OFF;
     return MM_OK;
 }
 
@@ -911,12 +998,15 @@ mm_status mm_render(mm_view v) {
         return flush_frame(v);
     }
     MM_TRY(next_stamp(v));
+    // no occlusion cull here: its records are built for displaced frames
     const mm::Launch b = mm::bin_launch(dim, v->desc.wrap != 0, mm::kRender,
                                         static_cast<int>(v->tuning.points_per_thread),
                                         v->tuning.bin_threads, v->args.c.n, v->ntiles);
-    void* bargs[] = {&v->bargs};
+    mm::BinArgs ba = v->bargs;
+    ba.v.cull = nullptr;
+    void* bargs[] = {&ba};
     MM_HIP(hipLaunchKernel(b.func, b.grid, b.block, bargs, b.shared, s));
-    for (size_t k = 1; k < v->nodes.size(); ++k) {
+    for (size_t k = v->frame_nodes; k < v->nodes.size(); ++k) {
         void* targs[] = {&v->targs};
         MM_HIP(hipLaunchKernel(v->nodes[k].func, v->nodes[k].grid, v->nodes[k].block, targs,
                                v->nodes[k].shared, s));
@@ -938,18 +1028,21 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
         first_arg = &v->args;
     }
     void* args[] = {first_arg};
-    hipKernelNodeParams pp = node_params(v->nodes[0], args);
+    MM_TRY(record_mark(v));
+    FrameGraph* fg = &v->plain;
     if (v->profiling && v->prof_count < v->prof_cap && v->prof_skip++ % v->prof_every == 0) {
         const uint32_t k = v->prof_count++;
-        for (int j = 0; j < 3; ++j)
+        for (int j = 0; j < kFrameEvents; ++j)
             MM_HIP(hipGraphExecEventRecordNodeSetEvent(v->timed.exec, v->timed.ev[j],
-                                                       v->events[3ull * k + j]));
-        MM_HIP(hipGraphExecKernelNodeSetParams(v->timed.exec, v->timed.first, &pp));
-        MM_HIP(hipGraphLaunch(v->timed.exec, v->inst->stream));
-        return MM_OK;
+                                                       v->events[static_cast<size_t>(kFrameEvents) * k + j]));
+        fg = &v->timed;
     }
-    MM_HIP(hipGraphExecKernelNodeSetParams(v->plain.exec, v->plain.first, &pp));
-    MM_HIP(hipGraphLaunch(v->plain.exec, v->inst->stream));
+    // the per-frame nodes (hint kernel and point pass) share one argument block
+    for (uint32_t j = 0; j < v->frame_nodes; ++j) {
+        hipKernelNodeParams pp = node_params(v->nodes[j], args);
+        MM_HIP(hipGraphExecKernelNodeSetParams(fg->exec, fg->per_frame[j], &pp));
+    }
+    MM_HIP(hipGraphLaunch(fg->exec, v->inst->stream));
     return MM_OK;
 }
 
@@ -1008,7 +1101,7 @@ mm_status mm_set_frame_overlap(mm_view v, uint32_t on) {
     // a splat left on auto becomes binned, which the overlap needs
     mm_tuning binned_auto{};
     const bool rebin = on && !binned(v) && v->req_splat == MM_SPLAT_AUTO;
-    if (rebin) MM_TRY(resolve_tuning(v->desc, mm_tuning{MM_SPLAT_BINNED, 0, 0, 0, 0, 0}, binned_auto));
+    if (rebin) MM_TRY(resolve_tuning(v->desc, mm_tuning{MM_SPLAT_BINNED, 0, 0, 0, 0, 0, 0}, binned_auto));
     if (on && !binned(v) && !rebin)
         return fail(MM_ERR_UNSUPPORTED, "set_frame_overlap: the view's splat was set to direct");
     if (on && !v->plain.exec) return fail(MM_ERR_INVALID_ARG, "set_frame_overlap: view has no usable tuning");
@@ -1067,7 +1160,7 @@ mm_status mm_profile_begin(mm_view v, uint32_t capacity) {
     MM_HIP(hipStreamSynchronize(v->inst->stream));
     destroy_graph(v->timed);
     for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
-    v->events.assign(3ull * capacity, nullptr);
+    v->events.assign(static_cast<size_t>(kFrameEvents) * capacity, nullptr);
     // timing only: no system-scope fence (a cache writeback and invalidate
     // per event would slow the frame being measured)
     for (auto& e : v->events) MM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
@@ -1095,22 +1188,67 @@ mm_status mm_profile_end(mm_view v, float* splat_ms, float* resolve_ms, float* f
     if (v->rstream) MM_HIP(hipStreamSynchronize(v->rstream));
     for (uint32_t k = 0; k < v->prof_count; ++k) {
         float t = 0.0f;
-        hipEvent_t* e = &v->events[3ull * k];
+        hipEvent_t* e = &v->events[static_cast<size_t>(kFrameEvents) * k];
         if (splat_ms) {
-            MM_HIP(hipEventElapsedTime(&t, e[0], e[1]));
+            MM_HIP(hipEventElapsedTime(&t, e[1], e[2]));
             splat_ms[k] = t;
         }
         if (resolve_ms) {
-            MM_HIP(hipEventElapsedTime(&t, e[1], e[2]));
+            MM_HIP(hipEventElapsedTime(&t, e[2], e[3]));
             resolve_ms[k] = t;
         }
         if (frame_ms) {
-            MM_HIP(hipEventElapsedTime(&t, e[0], e[2]));
+            MM_HIP(hipEventElapsedTime(&t, e[0], e[3]));
             frame_ms[k] = t;
         }
     }
     *count = v->prof_count;
     v->profiling = false;
+    return MM_OK;
+}
+
+mm_status mm_mark_begin(mm_view v, uint32_t capacity) {
+    MM_TRY(require_ready(v, "mark_begin"));
+    if (capacity < 2 || capacity > (1u << 20))
+        return fail(MM_ERR_INVALID_ARG, "mark_begin: capacity outside [2, 2^20]");
+    DeviceGuard guard(v->inst->device);
+    MM_HIP(hipStreamSynchronize(v->inst->stream));
+    for (hipEvent_t e : v->marks) (void)hipEventDestroy(e);
+    v->marks.assign(capacity, nullptr);
+    v->marking = false;
+    // timing only: no system-scope fence per mark
+    for (auto& e : v->marks) MM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    v->mark_cap = capacity;
+    v->mark_count = 0;
+    v->marking = true;
+    return MM_OK;
+}
+
+mm_status mm_mark_end(mm_view v) {
+    if (!v) return fail(MM_ERR_INVALID_ARG, "mark_end: null view");
+    if (!v->marking) return fail(MM_ERR_INVALID_ARG, "mark_end: no mark_begin");
+    DeviceGuard guard(v->inst->device);
+    if (v->mark_count < v->mark_cap) {  // close the last marked frame
+        MM_TRY(flush_frame(v));
+        MM_HIP(hipEventRecord(v->marks[v->mark_count++], v->inst->stream));
+    }
+    v->marking = false;
+    return MM_OK;
+}
+
+mm_status mm_mark_read(mm_view v, float* interval_ms, uint32_t* count) {
+    if (!v || !count) return fail(MM_ERR_INVALID_ARG, "mark_read: null argument");
+    if (v->marking) return fail(MM_ERR_INVALID_ARG, "mark_read: marks not ended (mm_mark_end)");
+    const uint32_t marks = v->mark_count;
+    if (marks < 2) return fail(MM_ERR_INVALID_ARG, "mark_read: fewer than two marks");
+    DeviceGuard guard(v->inst->device);
+    MM_HIP(hipEventSynchronize(v->marks[marks - 1]));
+    for (uint32_t k = 0; k + 1 < marks; ++k) {
+        float t = 0.0f;
+        MM_HIP(hipEventElapsedTime(&t, v->marks[k], v->marks[k + 1]));
+        if (interval_ms) interval_ms[k] = t;
+    }
+    *count = marks - 1;
     return MM_OK;
 }
 

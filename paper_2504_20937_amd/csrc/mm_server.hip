@@ -14,19 +14,16 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <limits>
-#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "mm_batch.h"
+#include "mm_sched.h"
 
 using namespace mmh;
-using Clock = std::chrono::steady_clock;
 
 namespace {
 
@@ -39,47 +36,23 @@ struct FrameBuf {
     uint64_t* border = nullptr;
     uint64_t* apron = nullptr;
     uint32_t* active = nullptr;
-};
-
-struct Session {
-    uint32_t width = 0, height = 0;
-    bool has_screen = false;
-    bool admitted = false;
-    bool busy = false;      // a request in flight
-    bool closing = false;
-    uint32_t queued = 0;    // requests submitted, not launched
-    uint64_t last_use = 0;  // launch counter when last launched (LRU)
-    FrameBuf buf;
+    bool fresh = false;    // new memory: its tile stamps are zeroed by its first launch
 };
 
 struct SCloud {
     mm::CloudArgs args{};
     uint64_t n = 0;
     mm_alloc alloc = nullptr;
-    uint32_t next_step = 0;
     uint32_t num_wg = 0;
     uint64_t* seg = nullptr;
     uint16_t* table = nullptr;
-    bool busy = false;
-    std::deque<uint64_t> queue;  // request ids in submission order
 };
 
-enum ReqState { kQueued = 0, kInFlight = 1, kDone = 2, kDropped = 3 };
-
-struct Request {
-    uint32_t session = 0, cloud = 0, step = 0;
-    float m[16] = {};
-    uint32_t width = 0, height = 0;
-    uint32_t* dev_out = nullptr;
-    Clock::time_point t_submit, t_done;
-    ReqState state = kQueued;
-};
+using Sched = mms::Scheduler<FrameBuf>;
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    bool busy = false;
-    std::vector<uint64_t> reqs;
     unsigned char* dev = nullptr;   // device copy of the table images
     size_t dev_bytes = 0;
     unsigned char* pinned = nullptr;   // host-coherent staging of the table images
@@ -94,7 +67,7 @@ struct Slot {
 
 }  // namespace
 
-struct mm_server_s {
+struct mm_server_s : Sched::Backend {
     mm_instance inst = nullptr;
     mm_server_desc desc{};
     uint32_t side = 64, shift = 6, ppt = 16, threads = 256, P = 4096, splits_cap = 2;
@@ -103,35 +76,24 @@ struct mm_server_s {
     std::condition_variable done_cv;  // request completion
     std::thread worker;
     bool stop = false;
-    bool failed = false;
     std::vector<SCloud> clouds;
-    std::unordered_map<uint32_t, Session> sessions;
-    std::unordered_map<uint64_t, Request> requests;
-    std::deque<uint64_t> pending;   // submission order
-    std::multimap<uint64_t, FrameBuf> pool;  // kept for reuse, by (width << 32 | height)
     std::vector<Slot> slots;
-    uint64_t held = 0;              // bytes of admitted and pooled frame buffers
-    uint64_t next_id = 1;
+    Sched* sched = nullptr;
     uint32_t stamp = 0;
     uint32_t* stamps = nullptr;     // one device word per slot
-    mm_server_stats stats{};
 
-    uint64_t fb_bytes(uint32_t w, uint32_t h) const;
-    mm_status alloc_buf(uint32_t w, uint32_t h, FrameBuf& out);
-    void free_buf(FrameBuf& b);
-    bool admit(Session& s);
-    void release(Session& s);
-    bool retire();
-    bool schedule();
-    mm_status launch(Slot& slot, const std::vector<uint64_t>& batch);
+    uint64_t fb_bytes(uint32_t w, uint32_t h) const override;
+    bool alloc_buf(uint32_t w, uint32_t h, FrameBuf& out) override;
+    void free_buf(FrameBuf& b) override;
+    bool launch(uint32_t slot, const std::vector<Sched::Item>& items) override;
+    int query(uint32_t slot) override;
+    mm_status launch_slot(Slot& slot, const std::vector<Sched::Item>& items);
     void run();
 };
 
 namespace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-
-uint64_t screen_key(uint32_t w, uint32_t h) { return (static_cast<uint64_t>(w) << 32) | h; }
 
 }  // namespace
 
@@ -148,12 +110,17 @@ uint64_t mm_server_s::fb_bytes(uint32_t w, uint32_t h) const {
     return b;
 }
 
-mm_status mm_server_s::alloc_buf(uint32_t w, uint32_t h, FrameBuf& out) {
+bool mm_server_s::alloc_buf(uint32_t w, uint32_t h, FrameBuf& out) {
     FrameBuf b;
     b.width = w;
     b.height = h;
     b.bytes = fb_bytes(w, h);
-    MM_HIP(hipMalloc(&b.base, b.bytes));
+    hipError_t e = hipMalloc(&b.base, b.bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        hip_fail(e, "server: allocating a frame buffer");
+        return false;
+    }
     const uint64_t nt = tiles_of(w, h, side);
     const uint64_t a = desc.footprint == 3 ? side + 2 : side;
     unsigned char* p = static_cast<unsigned char*>(b.base);
@@ -168,14 +135,13 @@ mm_status mm_server_s::alloc_buf(uint32_t w, uint32_t h, FrameBuf& out) {
         p += align_up(nt * 4 * side * 8, 256);
         b.apron = reinterpret_cast<uint64_t*>(p);
     }
-    // zero frame and tile stamps (older than any launch's stamp)
-    const hipError_t e = hipMemset(b.base, 0, b.bytes);
-    if (e != hipSuccess) {
-        (void)hipFree(b.base);
-        return hip_fail(e, "server: clearing a frame buffer");
-    }
+    // the tile stamps must read older than any launch's stamp: the first
+    // launch drawing into this buffer zeroes them on its own stream (a
+    // synchronous clear here would wait for the launches in flight); the
+    // frame and the partial tiles are written before they are read
+    b.fresh = true;
     out = b;
-    return MM_OK;
+    return true;
 }
 
 void mm_server_s::free_buf(FrameBuf& b) {
@@ -183,98 +149,28 @@ void mm_server_s::free_buf(FrameBuf& b) {
     b = FrameBuf{};
 }
 
-// Gives s a frame buffer: one kept for reuse at its screen size, else a new
-// one once the budget allows (freeing kept buffers of other sizes, then
-// evicting idle sessions, least recently used first).
-bool mm_server_s::admit(Session& s) {
-    const uint64_t need = fb_bytes(s.width, s.height);
-    const uint64_t key = screen_key(s.width, s.height);
-    for (;;) {
-        auto it = pool.find(key);
-        if (it != pool.end()) {
-            s.buf = it->second;
-            pool.erase(it);
-            break;
-        }
-        if (held + need <= desc.fb_budget_bytes) {
-            FrameBuf b;
-            if (alloc_buf(s.width, s.height, b) != MM_OK) return false;
-            held += b.bytes;
-            s.buf = b;
-            break;
-        }
-        if (!pool.empty()) {  // none of this size: free one kept buffer
-            auto p = pool.begin();
-            held -= p->second.bytes;
-            free_buf(p->second);
-            pool.erase(p);
-            continue;
-        }
-        Session* victim = nullptr;
-        for (auto& kv : sessions) {
-            Session& v = kv.second;
-            if (v.admitted && !v.busy && v.queued == 0 && &v != &s &&
-                (!victim || v.last_use < victim->last_use))
-                victim = &v;
-        }
-        if (!victim) return false;
-        pool.emplace(screen_key(victim->buf.width, victim->buf.height), victim->buf);
-        victim->buf = FrameBuf{};
-        victim->admitted = false;
-        stats.evictions++;
-    }
-    s.admitted = true;
-    stats.admissions++;
-    return true;
+int mm_server_s::query(uint32_t k) {
+    const hipError_t q = hipEventQuery(slots[k].done);
+    if (q == hipErrorNotReady) return 0;
+    if (q == hipSuccess) return 1;
+    fail(MM_ERR_HIP, "server: a launch failed: %s", hipGetErrorString(q));
+    return -1;
 }
 
-void mm_server_s::release(Session& s) {
-    if (!s.admitted) return;
-    pool.emplace(screen_key(s.buf.width, s.buf.height), s.buf);
-    s.buf = FrameBuf{};
-    s.admitted = false;
+bool mm_server_s::launch(uint32_t k, const std::vector<Sched::Item>& items) {
+    Slot& sl = slots[k];
+    if (launch_slot(sl, items) == MM_OK) return true;
+    (void)hipStreamSynchronize(sl.stream);
+    return false;
 }
 
-bool mm_server_s::retire() {
-    bool any = false;
-    for (Slot& sl : slots) {
-        if (!sl.busy) continue;
-        const hipError_t q = hipEventQuery(sl.done);
-        if (q == hipErrorNotReady) continue;
-        if (q != hipSuccess) {
-            failed = true;
-            fail(MM_ERR_HIP, "server: a launch failed: %s", hipGetErrorString(q));
-        }
-        const Clock::time_point now = Clock::now();
-        for (uint64_t id : sl.reqs) {
-            Request& r = requests[id];
-            r.state = q == hipSuccess ? kDone : kDropped;
-            r.t_done = now;
-            Session& s = sessions[r.session];
-            s.busy = false;
-            clouds[r.cloud].busy = false;
-            stats.completed++;
-            if (s.closing && s.queued == 0) {
-                release(s);
-                s.closing = false;
-                s.has_screen = false;
-            }
-        }
-        sl.reqs.clear();
-        sl.busy = false;
-        any = true;
-    }
-    if (any) done_cv.notify_all();
-    return any;
-}
-
-mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
+mm_status mm_server_s::launch_slot(Slot& sl, const std::vector<Sched::Item>& items) {
     std::vector<mmb::Cloud> cl;
     std::vector<mmb::PlanView> views;
-    for (uint64_t id : batch) {
-        const Request& r = requests[id];
+    for (const Sched::Item& it : items) {
+        const Sched::Request& r = *it.req;
         const SCloud& c = clouds[r.cloud];
-        Session& s = sessions[r.session];
+        const FrameBuf& buf = it.session->buf;
         mmb::Cloud x;
         x.args = c.args;
         x.args.step = r.step;
@@ -286,13 +182,13 @@ mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
         v.height = r.height;
         std::memcpy(v.view_proj, r.m, sizeof v.view_proj);
         v.full_clear = true;
-        v.colour = r.dev_out ? r.dev_out : s.buf.colour;
+        v.colour = r.dev_out ? r.dev_out : buf.colour;
         v.seg = c.seg;
         v.table = c.table;
-        v.part = s.buf.part;
-        v.border = s.buf.border;
-        v.apron = s.buf.apron;
-        v.active = s.buf.active;
+        v.part = buf.part;
+        v.border = buf.border;
+        v.apron = buf.apron;
+        v.active = buf.active;
         views.push_back(v);
     }
     mmb::shape_views(views, cl, side, P, desc.tuning.splits);
@@ -315,6 +211,12 @@ mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
         MM_HIP(hipHostGetDevicePointer(&sl.pinned_dev, sl.pinned, 0));
         sl.pinned_bytes = total * 2;
     }
+    for (const Sched::Item& it : items) {
+        FrameBuf& b = it.session->buf;
+        if (!b.fresh) continue;
+        MM_HIP(hipMemsetAsync(b.active, 0, tiles_of(b.width, b.height, side) * 4, sl.stream));
+        b.fresh = false;
+    }
     std::memcpy(sl.pinned, sl.img.stat.data(), stat);
     std::memcpy(sl.pinned + stat, sl.img.frame.data(), frame);
     // a kernel reads the staged tables: the slot's stream stays on the compute queue
@@ -322,12 +224,15 @@ mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
     mmb::bind_args(sl.img, sl.dev, sl.dev + stat, sl.stamp_slot, shift, P, sl.b, sl.t, sl.m);
     if (++stamp == 0) {
         // every older stamp must read as "not this launch": clear all of them
+        // once every other launch has finished reading them
         for (Slot& o : slots)
-            if (o.busy) MM_HIP(hipStreamSynchronize(o.stream));
-        for (auto& kv : sessions)
-            if (kv.second.admitted)
-                MM_HIP(hipMemset(kv.second.buf.active, 0, tiles_of(kv.second.width, kv.second.height, side) * 4));
-        for (auto& kv : pool) (void)hipMemset(kv.second.base, 0, kv.second.bytes);
+            if (&o != &sl) MM_HIP(hipStreamSynchronize(o.stream));
+        mm_status st = MM_OK;
+        sched->for_each_buf([&](FrameBuf& b) {
+            const hipError_t e = hipMemset(b.active, 0, tiles_of(b.width, b.height, side) * 4);
+            if (e != hipSuccess && st == MM_OK) st = hip_fail(e, "server: resetting tile stamps");
+        });
+        MM_TRY(st);
         stamp = 1;
     }
     sl.b.stamp = stamp;
@@ -338,73 +243,22 @@ mm_status mm_server_s::launch(Slot& sl, const std::vector<uint64_t>& batch) {
     return MM_OK;
 }
 
-bool mm_server_s::schedule() {
-    Slot* sl = nullptr;
-    for (Slot& s : slots)
-        if (!s.busy) {
-            sl = &s;
-            break;
-        }
-    if (!sl || pending.empty()) return false;
-    std::vector<uint64_t> batch;
-    for (uint64_t id : pending) {
-        Request& r = requests[id];
-        SCloud& c = clouds[r.cloud];
-        Session& s = sessions[r.session];
-        if (c.busy || c.queue.front() != id || s.busy) continue;
-        if (!s.admitted && !admit(s)) continue;
-        c.busy = true;
-        s.busy = true;
-        batch.push_back(id);
-        if (batch.size() >= desc.max_batch) break;
-    }
-    if (batch.empty()) return false;
-    for (uint64_t id : batch) {
-        Request& r = requests[id];
-        r.state = kInFlight;
-        clouds[r.cloud].queue.pop_front();
-        Session& s = sessions[r.session];
-        s.queued--;
-        s.last_use = stats.launches + 1;
-    }
-    pending.erase(std::remove_if(pending.begin(), pending.end(),
-                                 [&](uint64_t id) { return requests[id].state != kQueued; }),
-                  pending.end());
-    sl->reqs = batch;
-    sl->busy = true;
-    stats.launches++;
-    if (launch(*sl, batch) != MM_OK) {
-        // the launch did not go out: mark its requests dropped
-        failed = true;
-        (void)hipStreamSynchronize(sl->stream);
-        for (uint64_t id : batch) {
-            Request& r = requests[id];
-            r.state = kDropped;
-            r.t_done = Clock::now();
-            sessions[r.session].busy = false;
-            clouds[r.cloud].busy = false;
-        }
-        sl->reqs.clear();
-        sl->busy = false;
-        done_cv.notify_all();
-    }
-    return true;
-}
-
 void mm_server_s::run() {
     (void)hipSetDevice(inst->device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-        bool progressed = retire();
-        bool in_flight = false;
-        for (const Slot& s : slots) in_flight = in_flight || s.busy;
-        if (stop && !in_flight) break;
-        if (!stop && !failed) progressed = schedule() || progressed;
+        bool progressed = sched->retire();
+        if (progressed) done_cv.notify_all();
+        if (stop && !sched->in_flight()) break;
+        if (!stop && sched->schedule()) {
+            progressed = true;
+            done_cv.notify_all();  // a launch that did not go out dropped requests
+        }
         if (progressed) continue;
-        if (in_flight)
+        if (sched->in_flight())
             cv.wait_for(lk, std::chrono::microseconds(20));
         else
-            cv.wait(lk, [&] { return stop || (!pending.empty() && !failed); });
+            cv.wait(lk, [&] { return stop || (sched->has_pending() && !sched->failed()); });
     }
 }
 
@@ -470,6 +324,16 @@ mm_status mm_create_server(mm_instance inst, const mm_server_desc* desc, mm_serv
         delete srv;
         return hip_fail(e, "create_server: streams");
     }
+    srv->sched = new (std::nothrow) Sched(*srv, desc->fb_budget_bytes, desc->streams, desc->max_batch);
+    if (!srv->sched) {
+        for (Slot& sl : srv->slots) {
+            (void)hipEventDestroy(sl.done);
+            (void)hipStreamDestroy(sl.stream);
+        }
+        (void)hipFree(srv->stamps);
+        delete srv;
+        return fail(MM_ERR_OUT_OF_MEMORY, "create_server: host allocation");
+    }
     srv->worker = std::thread([srv] { srv->run(); });
     inst->servers.insert(srv);
     *out = srv;
@@ -483,9 +347,7 @@ mm_status mm_destroy_server(mm_server srv) {
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->stop = true;
-        for (auto& kv : srv->requests)
-            if (kv.second.state == kQueued) kv.second.state = kDropped;
-        srv->pending.clear();
+        srv->sched->drop_all_queued();
     }
     srv->cv.notify_all();
     srv->worker.join();
@@ -498,8 +360,8 @@ mm_status mm_destroy_server(mm_server srv) {
         (void)hipEventDestroy(sl.done);
         (void)hipStreamDestroy(sl.stream);
     }
-    for (auto& kv : srv->sessions) srv->free_buf(kv.second.buf);
-    for (auto& kv : srv->pool) srv->free_buf(kv.second);
+    srv->sched->free_all();
+    delete srv->sched;
     for (SCloud& c : srv->clouds) {
         if (c.seg) (void)hipFree(c.seg);
         if (c.table) (void)hipFree(c.table);
@@ -534,7 +396,7 @@ mm_status mm_server_add_cloud(mm_server srv, const mm_cloud_desc* c, uint32_t* c
     }
     c->position->users++;
     srv->clouds.push_back(std::move(sc));
-    *cloud_id = static_cast<uint32_t>(srv->clouds.size() - 1);
+    *cloud_id = srv->sched->add_cloud();
     return MM_OK;
 }
 
@@ -564,34 +426,21 @@ mm_status mm_server_submit(mm_server srv, uint32_t session, uint32_t cloud, cons
     }
     {
         std::lock_guard<std::mutex> lk(srv->mu);
-        if (srv->stop || srv->failed) return fail(MM_ERR_HIP, "server_submit: the server has stopped");
+        if (srv->stop || srv->sched->failed())
+            return fail(MM_ERR_HIP, "server_submit: the server has stopped");
         if (cloud >= srv->clouds.size())
             return fail(MM_ERR_INVALID_ARG, "server_submit: cloud %u of %zu", cloud, srv->clouds.size());
         if (srv->fb_bytes(width, height) > srv->desc.fb_budget_bytes)
             return fail(MM_ERR_BUDGET, "server_submit: a %ux%u frame buffer (%llu B) exceeds the budget",
                         width, height, (unsigned long long)srv->fb_bytes(width, height));
-        Session& s = srv->sessions[session];
-        if (s.has_screen && (s.width != width || s.height != height))
-            return fail(MM_ERR_INVALID_ARG, "server_submit: session %u is %ux%u, not %ux%u", session,
-                        s.width, s.height, width, height);
-        s.width = width;
-        s.height = height;
-        s.has_screen = true;
-        s.closing = false;
-        s.queued++;
-        const uint64_t id = srv->next_id++;
-        Request& r = srv->requests[id];
-        r.session = session;
-        r.cloud = cloud;
-        r.step = srv->clouds[cloud].next_step++;
-        std::memcpy(r.m, m, sizeof r.m);
-        r.width = width;
-        r.height = height;
-        r.dev_out = dev_out;
-        r.t_submit = Clock::now();
-        srv->pending.push_back(id);
-        srv->clouds[cloud].queue.push_back(id);
-        srv->stats.submitted++;
+        uint64_t id = 0;
+        const mm_status st = srv->sched->submit(session, cloud, m, width, height, dev_out, &id);
+        if (st == MM_ERR_INVALID_ARG) {
+            const Sched::Session* s = srv->sched->session(session);
+            return fail(st, "server_submit: session %u is %ux%u, not %ux%u", session, s ? s->width : 0u,
+                        s ? s->height : 0u, width, height);
+        }
+        if (st != MM_OK) return fail(st, "server_submit: refused");
         *request_id = id;
     }
     srv->cv.notify_all();
@@ -602,27 +451,30 @@ mm_status mm_server_poll(mm_server srv, uint64_t id, int32_t* done, double* late
     MM_TRY(server_ok(srv, "server_poll"));
     if (!done) return fail(MM_ERR_INVALID_ARG, "server_poll: null argument");
     std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->requests.find(id);
-    if (it == srv->requests.end()) return fail(MM_ERR_INVALID_ARG, "server_poll: unknown request %llu", (unsigned long long)id);
-    const Request& r = it->second;
-    if (r.state == kDropped) return fail(MM_ERR_HIP, "server_poll: request %llu was dropped", (unsigned long long)id);
-    *done = r.state == kDone ? 1 : 0;
-    if (latency_s && r.state == kDone) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+    const Sched::Request* r = srv->sched->request(id);
+    if (!r) return fail(MM_ERR_INVALID_ARG, "server_poll: unknown request %llu", (unsigned long long)id);
+    if (r->state == mms::kDropped)
+        return fail(MM_ERR_HIP, "server_poll: request %llu was dropped", (unsigned long long)id);
+    if (latency_s && r->state == mms::kDone)
+        *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    *done = r->state == mms::kDone ? 1 : 0;
     return MM_OK;
 }
 
 mm_status mm_server_wait(mm_server srv, uint64_t id, double* latency_s) {
     MM_TRY(server_ok(srv, "server_wait"));
     std::unique_lock<std::mutex> lk(srv->mu);
-    auto it = srv->requests.find(id);
-    if (it == srv->requests.end()) return fail(MM_ERR_INVALID_ARG, "server_wait: unknown request %llu", (unsigned long long)id);
+    if (!srv->sched->request(id))
+        return fail(MM_ERR_INVALID_ARG, "server_wait: unknown request %llu", (unsigned long long)id);
+    // a failed scheduler drops every queued request, so the state settles
     srv->done_cv.wait(lk, [&] {
-        const ReqState st = srv->requests[id].state;
-        return st == kDone || st == kDropped || srv->stop;
+        const mms::ReqState st = srv->sched->request(id)->state;
+        return st == mms::kDone || st == mms::kDropped || srv->stop;
     });
-    const Request& r = srv->requests[id];
-    if (r.state != kDone) return fail(MM_ERR_NOT_READY, "server_wait: request %llu did not complete", (unsigned long long)id);
-    if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
+    const Sched::Request* r = srv->sched->request(id);
+    if (r->state != mms::kDone)
+        return fail(MM_ERR_NOT_READY, "server_wait: request %llu did not complete", (unsigned long long)id);
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
     return MM_OK;
 }
 
@@ -630,31 +482,22 @@ mm_status mm_server_read_frame(mm_server srv, uint32_t session, void* host_rgba,
     MM_TRY(server_ok(srv, "server_read_frame"));
     if (!host_rgba) return fail(MM_ERR_INVALID_ARG, "server_read_frame: null argument");
     std::unique_lock<std::mutex> lk(srv->mu);
-    auto it = srv->sessions.find(session);
-    if (it == srv->sessions.end()) return fail(MM_ERR_INVALID_ARG, "server_read_frame: unknown session %u", session);
-    Session& s = it->second;
-    srv->done_cv.wait(lk, [&] { return !s.busy || srv->stop; });
-    if (!s.admitted) return fail(MM_ERR_NOT_READY, "server_read_frame: session %u holds no frame buffer", session);
-    const size_t need = static_cast<size_t>(s.width) * s.height * 4;
+    Sched::Session* s = srv->sched->session(session);
+    if (!s) return fail(MM_ERR_INVALID_ARG, "server_read_frame: unknown session %u", session);
+    srv->done_cv.wait(lk, [&] { return !s->busy || srv->stop; });
+    if (!s->admitted) return fail(MM_ERR_NOT_READY, "server_read_frame: session %u holds no frame buffer", session);
+    const size_t need = static_cast<size_t>(s->width) * s->height * 4;
     if (bytes < need) return fail(MM_ERR_INVALID_ARG, "server_read_frame: %zu bytes < %zu", bytes, need);
     DeviceGuard guard(srv->inst->device);
-    MM_HIP(hipMemcpy(host_rgba, s.buf.colour, need, hipMemcpyDeviceToHost));
+    MM_HIP(hipMemcpy(host_rgba, s->buf.colour, need, hipMemcpyDeviceToHost));
     return MM_OK;
 }
 
 mm_status mm_server_close_session(mm_server srv, uint32_t session) {
     MM_TRY(server_ok(srv, "server_close_session"));
     std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->sessions.find(session);
-    if (it == srv->sessions.end()) return fail(MM_ERR_INVALID_ARG, "server_close_session: unknown session %u", session);
-    Session& s = it->second;
-    if (!s.busy && s.queued == 0) {
-        srv->release(s);
-        s.closing = false;
-        s.has_screen = false;
-    } else {
-        s.closing = true;
-    }
+    if (!srv->sched->close_session(session))
+        return fail(MM_ERR_INVALID_ARG, "server_close_session: unknown session %u", session);
     srv->cv.notify_all();
     return MM_OK;
 }
@@ -663,12 +506,7 @@ mm_status mm_server_stats_get(mm_server srv, mm_server_stats* out) {
     MM_TRY(server_ok(srv, "server_stats_get"));
     if (!out) return fail(MM_ERR_INVALID_ARG, "server_stats_get: null argument");
     std::lock_guard<std::mutex> lk(srv->mu);
-    mm_server_stats s = srv->stats;
-    s.admitted_sessions = 0;
-    for (auto& kv : srv->sessions) s.admitted_sessions += kv.second.admitted ? 1u : 0u;
-    s.fb_bytes_in_use = srv->held;
-    s.queued = srv->pending.size();
-    *out = s;
+    *out = srv->sched->stats();
     return MM_OK;
 }
 

@@ -331,6 +331,11 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
                 out[static_cast<uint64_t>(ly) * v.width + lx] =
                     pixel_colour(keys[q], v.seed_lo, v.seed_hi, v.pal);
         }
+        if (v.hint) {  // the tile's winners, the next frame's occlusion hints
+            uint32_t* h = v.hint + static_cast<uint64_t>(t) * (S * S);
+            for (uint32_t q = tid; q < S * S; q += NT)
+                h[q] = keys[q] == kEmptyKey ? kNoHint : static_cast<uint32_t>(keys[q]);
+        }
     } else {
         write_part<FOOT, S, A, NT>(keys, v.part + static_cast<uint64_t>(piece) * (A * A));
     }
@@ -375,9 +380,18 @@ __global__ __launch_bounds__(kFusedThreads) void tile_fused_kernel(TileArgs a) {
     uint32_t t, z;
     tile_of_block(blockIdx.x, 1u, t, z);
     if (t >= a.v.ntiles) return;
+    if (a.v.cull) {  // read by this frame's bin pass; the next frame's hint kernel adds to it
+        uint32_t* rec = a.v.cull + static_cast<uint64_t>(t) * cull_words(S);
+        for (uint32_t w = threadIdx.x; w < cull_words(S); w += kFusedThreads) rec[w] = 0u;
+    }
     const uint32_t stamp = *a.stamp_in, flag = tile_flag(a.v, t);
     if (flag != stamp) {
-        if (flag == stamp - 1u || a.v.full_clear) clear_tile<SHIFT>(a.v, t, threadIdx.x, kFusedThreads);
+        if (flag == stamp - 1u || a.v.full_clear) {
+            clear_tile<SHIFT>(a.v, t, threadIdx.x, kFusedThreads);
+            if (a.v.hint)  // no winners now: no hints for the next frame
+                for (uint32_t q = threadIdx.x; q < S * S; q += kFusedThreads)
+                    a.v.hint[static_cast<uint64_t>(t) * (S * S) + q] = kNoHint;
+        }
         return;
     }
     tile_range<1, SHIFT, kFusedThreads, true>(a.v, t, 0u, a.v.num_wg, t, a.points_per_wg, keys, col);

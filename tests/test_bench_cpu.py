@@ -52,4 +52,5 @@ def test_traffic_counters_match_the_current_kernel_sources():
     # a different workload or tuning never borrows the counters
     e = b.TRAFFIC["bin_kernel"]
     assert b.measured_traffic("bin_kernel", "another-workload", e["tuning"]) is None
-    assert b.measured_traffic("bin_kernel", e["workload"], [2, 64, 8, 1, 1024, 0]) is None
+    assert b.measured_traffic("bin_kernel", e["workload"], [2, 64, 8, 1, 1024, 0, 2]) is None
+    assert b.measured_traffic("bin_kernel", e["workload"], e["tuning"][:6] + [1]) is None

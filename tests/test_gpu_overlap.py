@@ -40,6 +40,7 @@ def _overlap_run(rig, pts, w, h, foot, seed, amp, frames, cam_fn, tuning=None):
         mm.mm_set_tuning(view, *tuning)
     mm.mm_set_frame_overlap(view, True)
     say(f"  tuning {mm.mm_get_tuning(view)}")
+    assert mm.mm_get_tuning(view)[6] == mm.MM_CULL_OFF  # no occlusion cull with overlap
     ref = pts.copy()
     prev = np.zeros((h, w), dtype=np.uint32)  # the frame buffer starts cleared
     for s in range(frames):
@@ -98,8 +99,11 @@ def test_overlap_render_toggle_and_errors(rig):
     want = oracle.step_render(ref, seed, 4, amp, False, cam, w, h, 1)
     assert np.array_equal(mm.mm_read_frame(view, w, h), want)
     assert same_bits(rig.positions(dev), ref)
-    # direct splat and overlap exclude each other
+    # direct splat and overlap exclude each other; so do overlap and a cull asked for
     mm.mm_set_frame_overlap(view, True)
+    with pytest.raises(mm.MMError) as e:
+        mm.mm_set_tuning(view, 2, 32, 8, 1, 1024, 0xFFFFFFFF, mm.MM_CULL_ON)
+    assert e.value.status == mm.MM_ERR_UNSUPPORTED
     with pytest.raises(mm.MMError) as e:
         mm.mm_set_tuning(view, 1, 0, 0, 0, 0, 0)
     assert e.value.status == mm.MM_ERR_UNSUPPORTED

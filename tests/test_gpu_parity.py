@@ -43,7 +43,16 @@ SHAPES = [DIRECT, (2, 16, 4, 1, 256, ST), (2, 32, 8, 4, 256, ST), (2, 64, 16, 2,
 def _ids(modes):
     return ["direct" if m[0] == 1 else
             f"binned-t{m[1]}-p{m[2]}-n{m[4]}-" + (f"z{m[3]}" if m[5] == ST else f"r{m[5]}")
+            + ("-nocull" if len(m) > 6 and m[6] == 2 else "-cull" if len(m) > 6 and m[6] == 1 else "")
             for m in modes]
+
+
+# the occlusion cull (on by default where it applies: 3D, 1x1 footprint, one
+# static split) against the same shape with every record kept
+CULL_ON, CULL_OFF = 1, 2
+CULL_SHAPES = [(2, 32, 16, 1, 512, ST, CULL_ON), (2, 32, 8, 1, 1024, ST, CULL_OFF),
+               (2, 16, 4, 1, 256, ST, CULL_ON), (2, 64, 16, 1, 512, ST, CULL_ON),
+               (2, 32, 8, 1, 1024, ST, CULL_ON)]
 
 
 def _run(rig, pts, dim, w, h, foot, seed, amp, wrap, frames, cam_fn, check_every=1,
@@ -275,11 +284,130 @@ def test_resume_from_snapshot(rig):
     snap = rig.positions(dev).copy()
     dev2, alloc2 = rig.cloud(snap)
     view2 = rig.view(alloc2, 65536, 2, 512, 512, 1, 0, 0.005, True)
+    ref = snap.copy()
     for s in range(50, 60):
         mm.mm_step_render(view, s)
         mm.mm_step_render(view2, s)
-        assert np.array_equal(mm.mm_read_frame(view, 512, 512), mm.mm_read_frame(view2, 512, 512))
+        want = oracle.step_render(ref, 0, s, 0.005, True, synth.IDENTITY, 512, 512, 1)
+        got = mm.mm_read_frame(view2, 512, 512)
+        assert np.array_equal(got, want), f"resumed frame {s}: {first_diff(got, want)}"
+        assert np.array_equal(mm.mm_read_frame(view, 512, 512), got)
     assert same_bits(rig.positions(dev), rig.positions(dev2))
+    assert same_bits(rig.positions(dev2), ref)
+
+
+@pytest.mark.parametrize("mode", CULL_SHAPES, ids=_ids(CULL_SHAPES))
+def test_cull_orbit_many_frames(rig, mode):
+    """A dense cube under the orbit camera for 16 frames: from the second
+    frame on, the previous frame's winners rule out most records; every frame
+    and position equals the oracle's."""
+    say("case: occlusion cull, 3D uniform, 2^20 points, 480x270, 16 frames")
+    pts = synth.uniform_cube(1 << 20, seed=21)
+    _run(rig, pts, 3, 480, 270, 1, 21, 0.001, False, 16,
+         lambda s: synth.orbit_camera(s, 480, 270), mode=mode)
+
+
+@pytest.mark.parametrize("mode", CULL_SHAPES, ids=_ids(CULL_SHAPES))
+def test_cull_equal_depths_keep_the_smallest_index(rig, mode):
+    """Many copies of a few points (equal depth at one pixel, amplitude 0): a
+    record as deep as its pixel's bound is never ruled out, so the smallest
+    index still wins every frame."""
+    say("case: occlusion cull, 64 points repeated 500 times each, 128x96, 4 frames")
+    base = synth.uniform_cube(64, seed=22)
+    pts = np.ascontiguousarray(np.tile(base, (500, 1)))
+    _run(rig, pts, 3, 128, 96, 1, 22, 0.0, False, 4,
+         lambda s: synth.orbit_camera(0, 128, 96), mode=mode)
+
+
+@pytest.mark.parametrize("mode", CULL_SHAPES[:2], ids=_ids(CULL_SHAPES[:2]))
+def test_cull_wrap_3d(rig, mode):
+    say("case: occlusion cull with the 3D fold into [-1, 1)^3, a = 0.02, 200000 points, 320x240")
+    pts = (synth.uniform_cube(200000, seed=23) * 2.0 - 1.0).astype(np.float32)
+    cam = lambda s: synth.look_at_perspective((2.0 * np.sin(s * 0.05), 0.3, 2.0 * np.cos(s * 0.05)),
+                                              (0, 0, 0), (0, 1, 0), 60.0, 320 / 240)
+    _run(rig, pts, 3, 320, 240, 1, 23, 0.02, True, 6, cam, mode=mode)
+
+
+@pytest.mark.parametrize("mode", CULL_SHAPES[:1], ids=_ids(CULL_SHAPES[:1]))
+def test_cull_positions_rewritten_between_frames(rig, mode):
+    """The caller overwrites the positions between frames (a simulation of
+    its own): the hints then name points that are somewhere else entirely,
+    and the frames must still equal the oracle's."""
+    say("case: occlusion cull, positions replaced between frames, 300000 points, 400x300")
+    mm = rig.mm
+    n, w, h = 300000, 400, 300
+    pts = synth.uniform_cube(n, seed=24)
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, n, 3, w, h, 1, 24, 0.001, False, synth.orbit_camera(0, w, h))
+    mm.mm_set_tuning(view, *mode)
+    assert mm.mm_get_tuning(view)[6] == mm.MM_CULL_ON
+    ref = pts.copy()
+    for s in range(6):
+        cam = synth.orbit_camera(3 * s, w, h)
+        if s in (2, 4):
+            new = synth.gaussian_mixture(n, seed=100 + s, sigma=0.05)
+            rig.torch.cuda.synchronize()
+            dev.copy_(rig.torch.from_numpy(new))
+            rig.torch.cuda.synchronize()
+            ref = new.copy()
+        mm.mm_set_camera(view, cam)
+        mm.mm_step_render(view, s)
+        want = oracle.step_render(ref, 24, s, 0.001, False, cam, w, h, 1)
+        got = mm.mm_read_frame(view, w, h)
+        assert np.array_equal(got, want), f"frame {s}: {first_diff(got, want)}"
+    mm.mm_destroy_view(view)
+
+
+def _subnormal_cloud(n, seed):
+    """A 3D cloud with subnormal, signed-zero and normal coordinates mixed."""
+    rng = np.random.default_rng(seed)
+    pts = synth.uniform_cube(n, seed)
+    bits = pts.view(np.uint32)
+    # a third of the coordinates become subnormal (exponent field 0, mantissa
+    # non-zero), some negative; a few become -0.0
+    sub = rng.random(pts.shape) < 1 / 3
+    mant = rng.integers(1, 1 << 23, size=pts.shape, dtype=np.uint64).astype(np.uint32)
+    sign = (rng.random(pts.shape) < 0.5).astype(np.uint32) << 31
+    bits[sub] = (mant | sign)[sub]
+    negz = rng.random(pts.shape) < 0.01
+    bits[negz] = np.uint32(0x80000000)
+    assert np.count_nonzero((bits & 0x7F800000) == 0) > n // 2
+    return pts
+
+
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+@pytest.mark.parametrize("amp", [0.0, 0.001])
+def test_subnormal_coordinates_kept(rig, mode, amp):
+    """binary32 with subnormals (no flush to zero, no denormals-are-zero): with
+    amplitude 0 a subnormal coordinate is stored back unchanged (x + (+-0) = x),
+    and with a non-zero amplitude x + d rounds as IEEE arithmetic does."""
+    say(f"case: 3D cloud with subnormal coordinates, 40000 points, 256x192, amplitude {amp}")
+    pts = _subnormal_cloud(40000, 11)
+    _run(rig, pts, 3, 256, 192, 1, 5, amp, False, 3,
+         lambda s: synth.orbit_camera(s, 256, 192), mode=mode)
+
+
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_subnormal_coordinates_2d_wrap(rig, mode):
+    say("case: 2D cloud with subnormal coordinates, wrap, amplitude 0, 30000 points, 128x128")
+    pts = synth.uniform_square(30000, 12)
+    rng = np.random.default_rng(12)
+    bits = pts.view(np.uint32)
+    sub = rng.random(pts.shape) < 0.5
+    mant = rng.integers(1, 1 << 23, size=pts.shape, dtype=np.uint64).astype(np.uint32)
+    bits[sub] = mant[sub] | ((rng.random(pts.shape) < 0.5).astype(np.uint32) << 31)[sub]
+    _run(rig, pts, 2, 128, 128, 1, 6, 0.0, True, 2, lambda s: synth.IDENTITY, mode=mode)
+
+
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+@pytest.mark.parametrize("seed", [(1 << 32) + 7, 0xFEDCBA9876543210])
+def test_seed_above_2p32(rig, mode, seed):
+    """The key's high word is the seed's upper 32 bits: a seed of 2^32 or more
+    changes both the displacement draw and the colour hash."""
+    say(f"case: 3D uniform, seed {seed:#x}, 50001 points, 320x200, 3 frames")
+    pts = synth.uniform_cube(50001, seed=13)
+    _run(rig, pts, 3, 320, 200, 1, seed, 0.002, False, 3,
+         lambda s: synth.orbit_camera(2 * s, 320, 200), mode=mode)
 
 
 @pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
@@ -342,6 +470,42 @@ def test_profile_sampling_records_one_frame_in_every(rig, mode):
     assert sp.shape == (3,)
 
 
+@pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
+def test_frame_marks_time_every_frame(rig, mode):
+    say("case: mm_mark_begin/end around 12 frames (capacity 10), 2^18 points 640x480")
+    mm = rig.mm
+    pts = synth.uniform_cube(1 << 18, seed=6)
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, 1 << 18, 3, 640, 480, 1, 8, 0.002, False,
+                    synth.orbit_camera(0, 640, 480))
+    mm.mm_set_tuning(view, *mode)
+    with pytest.raises(RuntimeError):
+        mm.mm_mark_begin(view, 1)
+    with pytest.raises(RuntimeError):
+        mm.mm_mark_end(view)
+    mm.mm_mark_begin(view, 10)
+    mm.mm_profile_every(view, 4)
+    mm.mm_profile_begin(view, 3)
+    ref = pts.copy()
+    for s in range(12):  # frames 0..8 are marked; 9..11 find the marks full
+        cam = synth.orbit_camera(s, 640, 480)
+        mm.mm_set_camera(view, cam)
+        mm.mm_step_render(view, s)
+        want = oracle.step_render(ref, 8, s, 0.002, False, cam, 640, 480, 1)
+    with pytest.raises(RuntimeError):
+        mm.mm_mark_read(view, 10)  # still marking
+    mm.mm_mark_end(view)
+    iv = mm.mm_mark_read(view, 10)
+    sp, _, fr = mm.mm_profile_end(view, 3)
+    assert iv.shape == (9,) and np.all(iv > 0), iv
+    assert sp.shape == (3,)
+    # the marks span the frames they bracket: their sum is at least the
+    # graph time of the profiled frames among them
+    assert iv.sum() >= fr[:3].sum() * 0.99
+    assert np.array_equal(mm.mm_read_frame(view, 640, 480), want)
+    assert same_bits(rig.positions(dev), ref)
+
+
 def test_invalid_descriptions_are_rejected(rig):
     say("case: invalid view descriptions and wraps")
     mm = rig.mm
@@ -399,25 +563,34 @@ def test_tuning_choices_and_validation(rig):
     cam = synth.orbit_camera(0, 1920, 1080)
     view = rig.view(alloc, 5000, 3, 1920, 1080, 1, 0, 0.001, False, cam)
     # 5000 points on a 1080p screen: the direct splat (a small cloud)
-    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_DIRECT, 0, 0, 0, 0, 0)
+    OFF, ON = mm.MM_CULL_OFF, mm.MM_CULL_ON
+    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_DIRECT, 0, 0, 0, 0, 0, OFF)
     # binned by request: one bin workgroup, so one workgroup per tile in the depth test
     mm.mm_set_tuning(view, mm.MM_SPLAT_BINNED)
-    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST)
+    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST, OFF)
+    # the occlusion cull asked for: 512 threads of 16 points by default
+    mm.mm_set_tuning(view, mm.MM_SPLAT_BINNED, 0, 0, 0, 0, 0, ON)
+    assert mm.mm_get_tuning(view) == (mm.MM_SPLAT_BINNED, 32, 16, 1, 512, ST, ON)
     # 2^21 points (256 bin workgroups): the 1x1 footprint keeps one workgroup per
     # tile (which resolves the tile itself), the 3x3 footprint takes two splits
     n2 = 1 << 21
     dev2, alloc2 = rig.cloud(synth.uniform_cube(n2, seed=1))
     v1 = rig.view(alloc2, n2, 3, 1920, 1080, 1, 0, 0.001, False, cam)
-    assert mm.mm_get_tuning(v1) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST)
+    assert mm.mm_get_tuning(v1) == (mm.MM_SPLAT_BINNED, 32, 8, 1, 1024, ST, OFF)
     v3 = rig.view(alloc2, n2, 3, 1920, 1080, 3, 0, 0.001, False, cam)
-    assert mm.mm_get_tuning(v3) == (mm.MM_SPLAT_BINNED, 32, 8, 2, 1024, ST)
+    assert mm.mm_get_tuning(v3) == (mm.MM_SPLAT_BINNED, 32, 8, 2, 1024, ST, OFF)
     for bad, status in [((2, 128, 16, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
                         ((2, 32, 3, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
                         ((2, 32, 16, 3, 0, ST), mm.MM_ERR_INVALID_ARG),
                         ((2, 32, 16, 0, 384, 0), mm.MM_ERR_INVALID_ARG),
                         ((2, 32, 16, 0, 256, 512), mm.MM_ERR_INVALID_ARG),
                         ((7, 0, 0, 0, 0, 0), mm.MM_ERR_INVALID_ARG),
-                        ((2, 16, 16, 0, 0, 0), mm.MM_ERR_UNSUPPORTED)]:
+                        ((2, 16, 16, 0, 0, 0), mm.MM_ERR_UNSUPPORTED),
+                        ((2, 32, 8, 1, 1024, ST, 3), mm.MM_ERR_INVALID_ARG),
+                        ((1, 0, 0, 0, 0, 0, ON), mm.MM_ERR_UNSUPPORTED),
+                        ((2, 32, 8, 2, 1024, ST, ON), mm.MM_ERR_UNSUPPORTED),
+                        ((2, 32, 8, 0, 1024, 4096, ON), mm.MM_ERR_UNSUPPORTED),
+                        ((2, 32, 16, 1, 1024, ST, ON), mm.MM_ERR_UNSUPPORTED)]:
         with pytest.raises(mm.MMError) as e:
             mm.mm_set_tuning(view, *bad)
         assert e.value.status == status, (bad, str(e.value))
@@ -427,12 +600,14 @@ def test_tuning_choices_and_validation(rig):
     assert np.array_equal(mm.mm_read_frame(view, 1920, 1080),
                           oracle.step_render(ref, 0, 0, 0.001, False, cam, 1920, 1080, 1))
     mm.mm_set_tuning(view, 2, 64, 4, 8, 512, ST)
-    assert mm.mm_get_tuning(view) == (2, 64, 4, 8, 512, ST)
+    assert mm.mm_get_tuning(view) == (2, 64, 4, 8, 512, ST, OFF)
     mm.mm_step_render(view, 1)
     assert np.array_equal(mm.mm_read_frame(view, 1920, 1080),
                           oracle.step_render(ref, 0, 1, 0.001, False, cam, 1920, 1080, 1))
+    mm.mm_set_tuning(view, 2, 32, 8, 1, 1024, ST, OFF)
+    assert mm.mm_get_tuning(view) == (2, 32, 8, 1, 1024, ST, OFF)
     mm.mm_set_tuning(view, 1, 0, 0, 0, 0, 0)
-    assert mm.mm_get_tuning(view) == (1, 0, 0, 0, 0, 0)
+    assert mm.mm_get_tuning(view) == (1, 0, 0, 0, 0, 0, OFF)
 
 
 def test_largest_screen_falls_back_to_direct(rig):
@@ -455,6 +630,29 @@ def test_largest_screen_falls_back_to_direct(rig):
 @pytest.mark.parametrize("foot", [1, 3])
 @pytest.mark.parametrize("mode", SHAPES, ids=_ids(SHAPES))
 def test_frames_whose_tile_sets_change(rig, mode, foot):
+    _tile_sets_change(rig, mode, foot)
+
+
+CULL_ON_SHAPES = [m for m in CULL_SHAPES if m[6] == CULL_ON]
+
+
+@pytest.mark.parametrize("mode", CULL_ON_SHAPES, ids=_ids(CULL_ON_SHAPES))
+def test_cull_frames_whose_tile_sets_change(rig, mode):
+    """Camera jumps and render-only frames between culled frames: the hints
+    then name points far from where they land, or come from a frame drawn
+    without displacement."""
+    _tile_sets_change(rig, mode, 1)
+
+
+@pytest.mark.parametrize("mode", CULL_ON_SHAPES, ids=_ids(CULL_ON_SHAPES))
+def test_cull_uniform_ragged_small(rig, mode):
+    say("case: occlusion cull, 3D uniform, 65613 points (ragged), 320x240, 12 frames")
+    pts = synth.uniform_cube(65536 + 77, seed=3)
+    _run(rig, pts, 3, 320, 240, 1, 3, 0.001, False, 12,
+         lambda s: synth.orbit_camera(s, 320, 240), mode=mode)
+
+
+def _tile_sets_change(rig, mode, foot):
     say(f"case: consecutive frames drawing different tiles, footprint {foot}, mode {mode}")
     mm = rig.mm
     w, h = 640, 360

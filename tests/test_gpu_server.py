@@ -2,6 +2,8 @@
 cloud rendered alone after the same steps (the k-th request on a cloud
 displaces it with step k), whatever else was queued or in flight, under any
 batching, stream count and memory budget."""
+import time
+
 import numpy as np
 import pytest
 
@@ -61,12 +63,13 @@ def _serve(rig, clouds, sessions, order, budget, streams, max_batch, foot=1,
     reqs, outs, rids = [], [], []
     for s, c, f in order:
         w, h, deg = sessions[s]
-        cam = synth.orbit_camera(f, w, h, start_deg=deg)
-        out = torch.zeros((h, w), dtype=torch.int32, device="cuda")
-        torch.cuda.synchronize()
+        reqs.append((c, synth.orbit_camera(f, w, h, start_deg=deg), w, h))
+        outs.append(torch.zeros((h, w), dtype=torch.int32, device="cuda"))
+    # outputs ready before the first submission; no device-wide wait between
+    # submissions, so requests arrive while earlier launches run
+    torch.cuda.synchronize()
+    for (s, _, _), (c, cam, w, h), out in zip(order, reqs, outs):
         rids.append(mm.mm_server_submit(srv, s, c, cam, w, h, out.data_ptr()))
-        outs.append(out)
-        reqs.append((c, cam, w, h))
     lat = [mm.mm_server_wait(srv, r) for r in rids]
     stats = mm.mm_server_stats_get(srv)
     mm.mm_destroy_server(srv)
@@ -95,6 +98,79 @@ def test_server_results_equal_each_request_alone(rig, streams, max_batch):
     assert stats["completed"] == 48 and stats["submitted"] == 48
     assert all(x > 0 for x in lat)
     say(f"  launches {stats['launches']}, p50 latency {np.median(lat) * 1e3:.2f} ms")
+
+
+def test_server_served_screens_and_large_clouds(rig):
+    """The served workload's own screens (1280x720, 1920x1080, 3840x2160) and
+    clouds from the upper half of the batched set's sizes (2^20, 2^22
+    points), so that launches take two splits per tile and the merge, at
+    4K tile tables; every request against the oracle's replay of its cloud.
+    Requests arrive while launches are on the device: some launches carry
+    several requests, and two launches are in flight at once."""
+    clouds = _clouds(rig, [1 << 20, 1 << 22, 70000, (1 << 22) - 333])
+    sessions = {0: (1280, 720, 10.0), 1: (1920, 1080, 50.0), 2: (3840, 2160, 95.0),
+                3: (1280, 720, 140.0), 4: (1920, 1080, 185.0), 5: (3840, 2160, 230.0)}
+    rng = np.random.default_rng(17)
+    # a 4K request on a 2^22-point cloud first (about a millisecond on the
+    # device), then one on another cloud, which goes out on the second stream
+    # beside it; the rest arrive while those run and pack into launches
+    order = [(2, 1, 0), (0, 0, 1)] + [(int(rng.integers(0, 6)), int(rng.integers(0, 4)), f)
+                                      for f in range(2, 30)]
+    say(f"case: server, 4 clouds (2^20, 2^22, 70000, 2^22-333 points), 6 sessions at "
+        f"720p/1080p/4K, 30 requests, 2 streams, max_batch 8")
+    reqs, outs, lat, stats = _serve(rig, clouds, sessions, order, 1 << 36, 2, 8)
+    say(f"  stats {stats}")
+    want, refs = _expected(clouds, reqs, 1)
+    for k, (got, exp) in enumerate(zip(outs, want)):
+        g = got.cpu().numpy().view(np.uint32)
+        assert np.array_equal(g, exp), f"request {k} {order[k]}: {first_diff(g, exp)}"
+    for j, c in enumerate(clouds):
+        pos = rig.positions(c[1])
+        assert np.array_equal(pos.view(np.uint32), refs[j].view(np.uint32)), f"cloud {j} positions"
+    assert stats["completed"] == 30 and stats["dropped"] == 0
+    # continuous batching: fewer launches than requests, several requests in
+    # one launch, and a second launch sent while another was in flight
+    assert stats["launches"] < stats["completed"], stats
+    assert stats["max_batch"] >= 2, stats
+    assert stats["max_in_flight"] >= 2, stats
+
+
+def test_server_one_buffer_two_sessions_one_cloud(rig):
+    """Two sessions share a cloud under a budget of one frame buffer, with
+    submissions A0, B0, A1: after A0, B0 needs A's buffer while A still has
+    A1 queued. A must be evicted for B0 all the same, or the served loop has
+    nothing to run. Polled against a host deadline, so that a stall fails
+    the test instead of hanging it."""
+    mm = rig.mm
+    clouds = _clouds(rig, [20000])
+    w, h = 256, 256
+    # the budget: exactly one 256x256 frame buffer of this server's shape
+    # (RGBA8, two splits of 64x64-pixel u64 partial tiles, one stamp per tile)
+    budget = 256 * 256 * 4 + 16 * 2 * 64 * 64 * 8 + 256
+    srv = mm.mm_create_server(rig.inst, budget, 1, 8, 3, 1)
+    c = clouds[0]
+    mm.mm_server_add_cloud(srv, mm.make_cloud_desc(c[2], c[0].shape[0], 3, c[3], c[4]))
+    cams = [synth.orbit_camera(f, w, h, start_deg=30.0 * f) for f in range(3)]
+    say("case: server, budget of one 256x256 buffer, sessions A, B on one cloud: A0, B0, A1")
+    rids = [mm.mm_server_submit(srv, s, 0, cams[k], w, h) for k, s in enumerate([0, 1, 0])]
+    deadline = time.monotonic() + 30.0
+    while True:
+        done = [mm.mm_server_poll(srv, r)[0] for r in rids]
+        if all(done):
+            break
+        assert time.monotonic() < deadline, f"served loop stalled: done {done}, " \
+            f"stats {mm.mm_server_stats_get(srv)}"
+        time.sleep(0.002)
+    # the last request drew session A's frame: the cloud after steps 0, 1, 2
+    ref = c[0].copy()
+    for k in range(3):
+        oracle.displace(ref, c[3], k, c[4], False)
+    want = oracle.render(ref, c[3], cams[2], w, h, 1)
+    got = mm.mm_server_read_frame(srv, 0, w, h)
+    assert np.array_equal(got, want), first_diff(got, want)
+    st = mm.mm_server_stats_get(srv)
+    assert st["completed"] == 3 and st["evictions"] >= 2 and st["fb_bytes_in_use"] <= budget
+    mm.mm_destroy_server(srv)
 
 
 def test_server_small_budget_queues_and_evicts(rig):
