@@ -583,6 +583,37 @@ mm_status mm_server_close_session(mm_server server, uint32_t session);
 
 mm_status mm_server_stats_get(mm_server server, mm_server_stats* out);
 
+/* ------------------------------------------------- frames that allocate nothing
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): one frame of the
+ * direct splat (as mm_step_render with MM_SPLAT_DIRECT) on the caller's
+ * positions, frame and stream, with no instance, view or allocation. The
+ * per-pixel depth keys live in a file-scope device array of 2^22 keys
+ * (32 MiB, held by every device the library runs on until the process
+ * ends), so width * height may not exceed 2^22 (MM_ERR_BUDGET). The first
+ * call on a device fills the keys with the empty key; every frame leaves
+ * them empty. All calls on one device share the array: calls that overlap
+ * on a device (two streams, or two threads) race and may draw each other's
+ * points. Calls no hipMalloc or hipFree. Returns once the work is enqueued
+ * on `stream` (NULL: the null stream) of the current device. */
+typedef struct {
+    void* dev_positions;    /* element_count AoS points, displaced in place */
+    uint64_t element_count; /* 1 <= N <= 2^32 - 1 */
+    mm_domain domain;       /* MM_DOMAIN_2D: float2, MM_DOMAIN_3D: float3 */
+    uint32_t width;         /* even, in [2, 16384], width * height <= 2^22 */
+    uint32_t height;
+    uint32_t footprint;     /* 1 or 3 */
+    uint64_t seed;          /* as mm_view_desc */
+    float amplitude;
+    int32_t wrap;
+    uint32_t step;          /* displacement step of this frame */
+    float view_proj[16];    /* row-major clip-from-world; 3D only */
+    uint32_t* dev_rgba;     /* width * height RGBA8 words, written */
+    void* stream;           /* hipStream_t */
+} mm_static_frame_desc;
+
+mm_status mm_step_render_static(const mm_static_frame_desc* desc);
+
 /* ------------------------------------------------------------ diagnostics */
 const char* mm_status_string(mm_status status);
 const char* mm_last_error(void);

@@ -154,6 +154,24 @@ class mm_server_desc(C.Structure):
     ]
 
 
+class mm_static_frame_desc(C.Structure):
+    _fields_ = [
+        ("dev_positions", C.c_void_p),
+        ("element_count", C.c_uint64),
+        ("domain", C.c_int32),
+        ("width", C.c_uint32),
+        ("height", C.c_uint32),
+        ("footprint", C.c_uint32),
+        ("seed", C.c_uint64),
+        ("amplitude", C.c_float),
+        ("wrap", C.c_int32),
+        ("step", C.c_uint32),
+        ("view_proj", C.c_float * 16),
+        ("dev_rgba", C.c_void_p),
+        ("stream", C.c_void_p),
+    ]
+
+
 class mm_server_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "launches",
                                            "admitted_sessions", "admissions", "evictions",
@@ -203,6 +221,7 @@ def _declare(L):
         "mm_get_tuning": ([_vp, C.POINTER(mm_tuning)], _status),
         "mm_profile_begin": ([_vp, C.c_uint32], _status),
         "mm_profile_every": ([_vp, C.c_uint32], _status),
+        "mm_step_render_static": ([C.POINTER(mm_static_frame_desc)], _status),
         "mm_mark_begin": ([_vp, C.c_uint32], _status),
         "mm_mark_end": ([_vp], _status),
         "mm_mark_read": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
@@ -537,6 +556,26 @@ def mm_mark_read(view: int, capacity: int) -> np.ndarray:
     n = C.c_uint32()
     _check(lib().mm_mark_read(view, _fptr(out), C.byref(n)), "mm_mark_read")
     return out[:n.value]
+
+
+def mm_step_render_static(dev_positions: int, element_count: int, dim: int, width: int,
+                          height: int, dev_rgba: int, step: int, footprint: int = 1,
+                          seed: int = 0, amplitude: float = 0.0, wrap: bool = False,
+                          view_proj=None, stream: int = 0) -> None:
+    """One direct-splat frame with no allocation (keys in the library's static array)."""
+    d = mm_static_frame_desc()
+    d.dev_positions = dev_positions
+    d.element_count = element_count
+    d.domain = MM_DOMAIN_2D if dim == 2 else MM_DOMAIN_3D
+    d.width, d.height, d.footprint = width, height, footprint
+    d.seed, d.amplitude, d.wrap, d.step = seed, amplitude, int(bool(wrap)), step
+    m = np.eye(4, dtype=np.float32) if view_proj is None else view_proj
+    m = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(16))
+    for k in range(16):
+        d.view_proj[k] = float(m[k])
+    d.dev_rgba = dev_rgba
+    d.stream = stream or None
+    _check(lib().mm_step_render_static(C.byref(d)), "mm_step_render_static")
 
 
 # ------------------------------------------------------------------- batches

@@ -60,6 +60,7 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.mm_profile_every(None, 4) == mm.MM_ERR_INVALID_ARG
     assert L.mm_mark_begin(None, 4) == mm.MM_ERR_INVALID_ARG
     assert L.mm_mark_end(None) == mm.MM_ERR_INVALID_ARG
+    assert L.mm_step_render_static(None) == mm.MM_ERR_INVALID_ARG
     n = C.c_uint32(77)
     assert L.mm_mark_read(None, None, C.byref(n)) == mm.MM_ERR_INVALID_ARG
     assert n.value == 77  # out-param untouched
