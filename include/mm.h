@@ -15,8 +15,10 @@
  *
  * Conventions for every call:
  *  - The return value is an mm_status: MM_OK (0) or a negative error code.
- *    On error, out-parameters are left untouched and mm_last_error() gives
- *    a thread-local message.
+ *    On error, out-parameters are left untouched, what the call allocated
+ *    is freed, and mm_last_error() gives a thread-local message. A call that
+ *    reshapes an object (mm_set_tuning, mm_set_frame_overlap,
+ *    mm_batch_set_tuning) and fails puts back the shape the object had.
  *  - Pointers named dev_* are device addresses; every other pointer is host
  *    memory owned by the caller and only read or written during the call.
  *  - Calls on one instance (and on its views, batches) must be serialised
@@ -194,7 +196,8 @@ mm_status mm_set_colour(mm_view view, const mm_colour_desc* desc);
  * Reallocates the view's scratch (a second set of records, table and tile
  * stamps) and synchronises. A view whose splat was left on auto switches to
  * the binned splat (auto shapes); MM_ERR_UNSUPPORTED when the direct splat
- * was asked for; mm_set_tuning to a direct splat is refused while it is on. */
+ * was asked for; mm_set_tuning to a direct splat is refused while it is on.
+ * On failure the view keeps its mode and tuning, as mm_set_tuning. */
 mm_status mm_set_frame_overlap(mm_view view, uint32_t on);
 
 /* Overlapped views: draws the frame of the last mm_step_render (the pending
@@ -273,7 +276,10 @@ typedef struct {
  * view's scratch buffers and rebuilds its graph. Synchronises. Returns
  * MM_ERR_UNSUPPORTED for a shape the screen cannot use (more than 4096 tiles, or
  * a bin workgroup whose LDS, 8 * bin_threads * points_per_thread + 4 * (tiles + 1)
- * bytes, exceeds 160 KiB). */
+ * bytes, exceeds 160 KiB). On any failure the view keeps the tuning it had;
+ * only if that tuning's scratch cannot be had again either is the view left
+ * without a splat (its frames then return MM_ERR_INVALID_ARG) until a later
+ * mm_set_tuning succeeds. */
 mm_status mm_set_tuning(mm_view view, const mm_tuning* tuning);
 
 /* The resolved strategy and shape in use (never MM_SPLAT_AUTO; fields a
@@ -476,7 +482,8 @@ typedef struct {
 } mm_batch_tuning;
 
 /* Chooses the shape for later frames; reallocates scratch and rebuilds the
- * graph. Synchronises. */
+ * graph. Synchronises. On failure the batch keeps the shape it had (or, if
+ * that cannot be set up again, has none until a later call succeeds). */
 mm_status mm_batch_set_tuning(mm_batch batch, const mm_batch_tuning* tuning);
 mm_status mm_batch_get_tuning(mm_batch batch, mm_batch_tuning* out);
 
@@ -613,6 +620,13 @@ typedef struct {
 } mm_static_frame_desc;
 
 mm_status mm_step_render_static(const mm_static_frame_desc* desc);
+
+/* ---------------------------------------------------------------- testing
+ * For tests of the error paths: the next `after` device or pinned host
+ * allocations the library makes succeed and the one after them fails as if
+ * memory were short (MM_ERR_OUT_OF_MEMORY from the call that made it), once;
+ * negative: no allocation is made to fail (the default). Process-wide. */
+mm_status mm_debug_fail_allocations(int64_t after);
 
 /* ------------------------------------------------------------ diagnostics */
 const char* mm_status_string(mm_status status);

@@ -17,7 +17,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mm_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# MM_ORACLE_LIB names another build of mm_oracle.c to load instead (the
+# sanitizer test loads one built with AddressSanitizer and UBSan); it is used
+# as built, never rebuilt here.
+LIB = os.environ.get("MM_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
           "-fexcess-precision=standard", "-fPIC", "-shared", "-Wall", "-Wextra"]
 EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
@@ -25,6 +28,8 @@ EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (also called by the package build)."""
+    if os.environ.get("MM_ORACLE_LIB"):
+        return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(
             os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "mm_oracle.h"))):
         tmp = LIB + ".tmp"
@@ -54,6 +59,8 @@ def lib() -> C.CDLL:
         L.oracle_project.argtypes = [f32p, C.c_uint32, f32p, C.c_uint32, C.c_uint32,
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), u32p]
         L.oracle_project.restype = C.c_int
+        L.oracle_project_many.argtypes = [f32p, C.c_uint64, C.c_uint32, f32p, C.c_uint32,
+                                          C.c_uint32, C.POINTER(C.c_int64)]
         L.oracle_splat.argtypes = [f32p, C.c_uint64, C.c_uint32, f32p, C.c_uint32,
                                    C.c_uint32, C.c_uint32, u64p, u64p]
         L.oracle_colour.argtypes = [C.c_uint32, C.c_uint64]
@@ -122,6 +129,17 @@ def project(p, m, width: int, height: int):
     ok = lib().oracle_project(_ptr(p, C.c_float), p.shape[0], _ptr(m, C.c_float),
                               width, height, C.byref(px), C.byref(py), C.byref(bits))
     return (px.value, py.value, bits.value) if ok else None
+
+
+def project_many(pos: np.ndarray, m, width: int, height: int) -> np.ndarray:
+    """Pixel index py * width + px of every point of an (n, dim) float32
+    array, -1 for points off screen (the projection of ``project``)."""
+    assert pos.dtype == np.float32 and pos.ndim == 2 and pos.flags.c_contiguous
+    m = _mat(m)
+    out = np.empty(pos.shape[0], dtype=np.int64)
+    lib().oracle_project_many(_ptr(pos, C.c_float), pos.shape[0], pos.shape[1],
+                              _ptr(m, C.c_float), width, height, _ptr(out, C.c_int64))
+    return out
 
 
 def new_depth(width: int, height: int) -> np.ndarray:

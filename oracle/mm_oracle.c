@@ -170,6 +170,17 @@ int oracle_project(const float* p, uint32_t dim, const float m[16],
     return 1;
 }
 
+void oracle_project_many(const float* pos, uint64_t n, uint32_t dim, const float m[16],
+                         uint32_t width, uint32_t height, int64_t* pixel)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        int32_t px, py;
+        uint32_t bits;
+        pixel[i] = oracle_project(pos + i * dim, dim, m, width, height, &px, &py, &bits)
+                       ? (int64_t)py * width + px : -1;
+    }
+}
+
 /* Markers of one size (section "Performance Benchmark") drawn as a square
  * footprint of 1 or 3 pixels a side. Each covered pixel keeps the smallest
  * (depth, index) key: the nearest point wins, and equal depths go to the

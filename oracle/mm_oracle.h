@@ -56,6 +56,11 @@ int oracle_project(const float* p, uint32_t dim, const float m[16],
                    uint32_t width, uint32_t height,
                    int32_t* px, int32_t* py, uint32_t* depth_bits);
 
+/* oracle_project for points 0..n-1 of an AoS array: pixel index
+ * py * width + px of each point that lands on screen, else -1. */
+void oracle_project_many(const float* pos, uint64_t n, uint32_t dim, const float m[16],
+                         uint32_t width, uint32_t height, int64_t* pixel);
+
 /* Depth-resolved splat. For every point (in the order order[0..n-1] when
  * order is not NULL, else 0..n-1) that projects on screen, every pixel of
  * its footprint (1: the pixel itself; 3: the 3x3 block around it, each

@@ -222,6 +222,7 @@ def _declare(L):
         "mm_profile_begin": ([_vp, C.c_uint32], _status),
         "mm_profile_every": ([_vp, C.c_uint32], _status),
         "mm_step_render_static": ([C.POINTER(mm_static_frame_desc)], _status),
+        "mm_debug_fail_allocations": ([C.c_int64], _status),
         "mm_mark_begin": ([_vp, C.c_uint32], _status),
         "mm_mark_end": ([_vp], _status),
         "mm_mark_read": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_uint32)], _status),
@@ -556,6 +557,11 @@ def mm_mark_read(view: int, capacity: int) -> np.ndarray:
     n = C.c_uint32()
     _check(lib().mm_mark_read(view, _fptr(out), C.byref(n)), "mm_mark_read")
     return out[:n.value]
+
+
+def mm_debug_fail_allocations(after: int) -> None:
+    """Lets `after` library allocations succeed and fails the next one (tests)."""
+    _check(lib().mm_debug_fail_allocations(after), "mm_debug_fail_allocations")
 
 
 def mm_step_render_static(dev_positions: int, element_count: int, dim: int, width: int,

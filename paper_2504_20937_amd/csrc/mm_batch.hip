@@ -292,12 +292,12 @@ mm_status Plan::setup(mm_instance inst, const mm_batch_tuning& t) {
     stamp = 0;
 
     MM_TRY(build_tables(clouds, views, P, footprint, img));
-    MM_HIP(hipMalloc(&dev_static, img.stat.size()));
+    MM_HIP(dev_malloc(&dev_static, img.stat.size()));
     MM_HIP(hipMemcpyAsync(dev_static, img.stat.data(), img.stat.size(), hipMemcpyHostToDevice, s));
     MM_HIP(hipStreamSynchronize(s));
-    MM_HIP(hipMalloc(&dev_frame, img.frame.size()));
+    MM_HIP(dev_malloc(&dev_frame, img.frame.size()));
     for (int j = 0; j < kRing; ++j) {
-        MM_HIP(hipHostMalloc(&ring[j], img.frame.size(), hipHostMallocCoherent));
+        MM_HIP(pinned_malloc(&ring[j], img.frame.size()));
         MM_HIP(hipHostGetDevicePointer(&ring_dev[j], ring[j], 0));
         // marks the upload kernel's reads of slot j done: no cache flush needed
         MM_HIP(hipEventCreateWithFlags(&ring_ev[j], hipEventDisableTiming | hipEventDisableSystemFence));
@@ -583,13 +583,20 @@ mm_status mm_batch_set_tuning(mm_batch b, const mm_batch_tuning* req) {
     MM_TRY(b->plan.resolve(*req, t));
     DeviceGuard guard(b->inst->device);
     MM_HIP(hipStreamSynchronize(b->inst->stream));
+    const mm_batch_tuning old = b->plan.tuning;
+    const bool had = b->plan.exec != nullptr;
     b->plan.free_scratch();
     b->profiling = false;
     mm_status st = b->plan.setup(b->inst, t);
     if (st == MM_OK) st = b->plan.build_graph();
-    if (st != MM_OK) {
+    if (st != MM_OK) {  // back to the tuning the batch had, keeping this message
+        const std::string first = mm_last_error();
         (void)hipStreamSynchronize(b->inst->stream);
-        b->plan.free_scratch();  // unusable until a tuning succeeds
+        b->plan.free_scratch();
+        mm_status back = had ? b->plan.setup(b->inst, old) : st;
+        if (back == MM_OK) back = b->plan.build_graph();
+        if (back != MM_OK) b->plan.free_scratch();  // unusable until a tuning succeeds
+        (void)fail(st, "%s", first.c_str());
     }
     return st;
 }
@@ -632,7 +639,7 @@ mm_status mm_batch_autotune(mm_batch b, uint32_t frames, mm_batch_tuning* out) {
     hipError_t e = hipSuccess;
     for (size_t c = 0; c < p.clouds.size() && e == hipSuccess; ++c) {
         const size_t bytes = p.clouds[c].n * stride;
-        e = hipMalloc(&saved[c], bytes);
+        e = dev_malloc(&saved[c], bytes);
         if (e == hipSuccess)
             e = hipMemcpyAsync(saved[c], p.clouds[c].args.pos, bytes, hipMemcpyDeviceToDevice, inst->stream);
     }

@@ -138,9 +138,14 @@ inline hipError_t launch(const mm::Launch& l, void* arg, hipStream_t s) {
     return hipLaunchKernel(l.func, l.grid, l.block, args, l.shared, s);
 }
 
+// Every device and pinned host allocation of the library goes through these,
+// so that a test can make one of them fail (mm_debug_fail_allocations).
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t pinned_malloc(void** p, size_t bytes);
+
 template <typename T>
 hipError_t alloc_n(T** p, uint64_t n) {
-    return hipMalloc(reinterpret_cast<void**>(p), (n ? n : 1) * sizeof(T));
+    return dev_malloc(reinterpret_cast<void**>(p), (n ? n : 1) * sizeof(T));
 }
 
 // Checks a cloud: format, count against its alloc, amplitude and wrap.

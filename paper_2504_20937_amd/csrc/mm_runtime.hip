@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -602,9 +603,62 @@ void destroy_overlap(mm_view v) {
     v->overlap = false;
 }
 
+// The render stream and events of frame overlap; on failure none is kept.
+hipError_t open_overlap(mm_view v) {
+    hipError_t e = hipStreamCreateWithFlags(&v->rstream, hipStreamNonBlocking);
+    for (hipEvent_t* ev : {&v->ev_bin[0], &v->ev_bin[1], &v->ev_drawn[0], &v->ev_drawn[1]})
+        // ordering between two streams of one device: a device-scope release
+        if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventReleaseToDevice);
+    if (e != hipSuccess) {
+        destroy_overlap(v);
+        return e;
+    }
+    v->overlap = true;
+    return hipSuccess;
+}
+
+// After a failed change of tuning or mode: the splat of the tuning the view
+// had. If even that cannot be set up the view has no splat (its frames then
+// fail with MM_ERR_INVALID_ARG) until a later mm_set_tuning succeeds. The
+// message of the first failure is kept.
+void restore_splat(mm_view v, const mm_tuning& t, uint32_t req_splat) {
+    const std::string first = g_last_error;
+    teardown_splat(v);
+    v->tuning = t;
+    v->req_splat = req_splat;
+    if (setup_splat(v) != MM_OK) teardown_splat(v);
+    g_last_error = first;
+}
+
+}  // namespace
+
+namespace {
+
+// Allocations to let through before one fails (mm_debug_fail_allocations);
+// negative: none fails.
+std::atomic<int64_t> g_fail_after{-1};
+
+bool inject_failure() {
+    int64_t n = g_fail_after.load(std::memory_order_relaxed);
+    while (n >= 0) {
+        if (g_fail_after.compare_exchange_weak(n, n - 1, std::memory_order_relaxed)) return n == 0;
+    }
+    return false;
+}
+
 }  // namespace
 
 namespace mmh {
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    if (inject_failure()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_malloc(void** p, size_t bytes) {
+    if (inject_failure()) return hipErrorOutOfMemory;
+    return hipHostMalloc(p, bytes, hipHostMallocCoherent);
+}
 
 mm_status fail(mm_status st, const char* fmt, ...) {
     char buf[512];
@@ -664,6 +718,11 @@ mm_status validate_camera(const float m[16], const char* what) {
 extern "C" {
 
 int32_t mm_version(void) { return 200; }
+
+mm_status mm_debug_fail_allocations(int64_t after) {
+    g_fail_after.store(after < 0 ? -1 : after, std::memory_order_relaxed);
+    return MM_OK;
+}
 
 const char* mm_last_error(void) { return g_last_error.c_str(); }
 
@@ -767,7 +826,7 @@ mm_status mm_alloc_linear(mm_instance inst, size_t bytes, void** dev_ptr, mm_all
     if (bytes == 0) return fail(MM_ERR_INVALID_ARG, "alloc_linear: zero bytes");
     DeviceGuard guard(inst->device);
     void* p = nullptr;
-    MM_HIP(hipMalloc(&p, bytes));
+    MM_HIP(dev_malloc(&p, bytes));
     mm_alloc a = new (std::nothrow) mm_alloc_s{inst, p, bytes, true, 0};
     if (!a) {
         (void)hipFree(p);
@@ -880,11 +939,13 @@ mm_status mm_set_tuning(mm_view v, const mm_tuning* req) {
     DeviceGuard guard(v->inst->device);
     MM_TRY(flush_frame(v));
     MM_HIP(hipStreamSynchronize(v->inst->stream));
+    const mm_tuning old_tuning = v->tuning;
+    const uint32_t old_req = v->req_splat;
     teardown_splat(v);
     v->tuning = t;
     v->req_splat = req->splat;
     const mm_status st = setup_splat(v);
-    if (st != MM_OK) teardown_splat(v);  // the view is unusable until a tuning succeeds
+    if (st != MM_OK) restore_splat(v, old_tuning, old_req);
     return st;
 }
 
@@ -905,7 +966,7 @@ mm_status mm_autotune(mm_view v, uint32_t frames, mm_tuning* out) {
     }
     const size_t bytes = static_cast<size_t>(d.element_count) * 4u * static_cast<size_t>(d.format);
     void* saved = nullptr;
-    MM_HIP(hipMalloc(&saved, bytes));
+    MM_HIP(dev_malloc(&saved, bytes));
     hipError_t e = hipMemcpyAsync(saved, v->position->ptr, bytes, hipMemcpyDeviceToDevice, inst->stream);
     std::vector<mm_tuning> cands;
     if (!v->overlap) cands.push_back({MM_SPLAT_DIRECT, 0, 0, 0, 0, 0, 0});
@@ -1108,23 +1169,23 @@ mm_status mm_set_frame_overlap(mm_view v, uint32_t on) {
     DeviceGuard guard(v->inst->device);
     MM_TRY(flush_frame(v));
     MM_HIP(hipStreamSynchronize(v->inst->stream));
+    const mm_tuning old_tuning = v->tuning;
+    const bool was_on = v->overlap;
     teardown_splat(v);
     destroy_overlap(v);
     if (rebin) v->tuning = binned_auto;
+    mm_status st = MM_OK;
     if (on) {
-        hipError_t e = hipStreamCreateWithFlags(&v->rstream, hipStreamNonBlocking);
-        for (hipEvent_t* ev : {&v->ev_bin[0], &v->ev_bin[1], &v->ev_drawn[0], &v->ev_drawn[1]})
-            // ordering between two streams of one device: a device-scope release
-            if (e == hipSuccess) e = hipEventCreateWithFlags(ev, hipEventDisableTiming | hipEventReleaseToDevice);
-        if (e != hipSuccess) {
-            destroy_overlap(v);
-            (void)setup_splat(v);
-            return hip_fail(e, "set_frame_overlap: render stream");
-        }
-        v->overlap = true;
+        const hipError_t e = open_overlap(v);
+        if (e != hipSuccess) st = hip_fail(e, "set_frame_overlap: render stream");
     }
-    const mm_status st = setup_splat(v);
-    if (st != MM_OK) teardown_splat(v);
+    if (st == MM_OK) st = setup_splat(v);
+    if (st != MM_OK) {  // back to the mode and tuning the view had
+        teardown_splat(v);
+        destroy_overlap(v);
+        if (was_on) (void)open_overlap(v);
+        restore_splat(v, old_tuning, v->req_splat);
+    }
     return st;
 }
 

@@ -115,7 +115,7 @@ bool mm_server_s::alloc_buf(uint32_t w, uint32_t h, FrameBuf& out) {
     b.width = w;
     b.height = h;
     b.bytes = fb_bytes(w, h);
-    hipError_t e = hipMalloc(&b.base, b.bytes);
+    hipError_t e = dev_malloc(&b.base, b.bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         hip_fail(e, "server: allocating a frame buffer");
@@ -199,7 +199,7 @@ mm_status mm_server_s::launch_slot(Slot& sl, const std::vector<Sched::Item>& ite
         if (sl.dev) (void)hipFree(sl.dev);
         sl.dev = nullptr;
         sl.dev_bytes = 0;
-        MM_HIP(hipMalloc(reinterpret_cast<void**>(&sl.dev), total * 2));
+        MM_HIP(dev_malloc(reinterpret_cast<void**>(&sl.dev), total * 2));
         sl.dev_bytes = total * 2;
     }
     if (total > sl.pinned_bytes) {
@@ -207,7 +207,7 @@ mm_status mm_server_s::launch_slot(Slot& sl, const std::vector<Sched::Item>& ite
         sl.pinned = nullptr;
         sl.pinned_dev = nullptr;
         sl.pinned_bytes = 0;
-        MM_HIP(hipHostMalloc(reinterpret_cast<void**>(&sl.pinned), total * 2, hipHostMallocCoherent));
+        MM_HIP(pinned_malloc(reinterpret_cast<void**>(&sl.pinned), total * 2));
         MM_HIP(hipHostGetDevicePointer(&sl.pinned_dev, sl.pinned, 0));
         sl.pinned_bytes = total * 2;
     }
@@ -306,7 +306,7 @@ mm_status mm_create_server(mm_instance inst, const mm_server_desc* desc, mm_serv
     srv->P = threads * ppt;
     srv->splits_cap = t.splits ? t.splits : 2u;
     srv->desc.tuning = mm_batch_tuning{side, ppt, t.splits, t.grid_blocks, threads};
-    hipError_t e = hipMalloc(&srv->stamps, 256 * desc->streams);
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(&srv->stamps), 256 * desc->streams);
     if (e == hipSuccess) e = hipMemset(srv->stamps, 0, 256 * desc->streams);
     srv->slots.resize(desc->streams);
     for (uint32_t k = 0; k < desc->streams && e == hipSuccess; ++k) {

@@ -10,7 +10,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(os.path.dirname(_HERE), "libmm_hostcopy.so")
+# MM_HOSTCOPY_LIB names another build of hostcopy.c to load instead (the
+# sanitizer test loads one built with AddressSanitizer and UBSan).
+LIB_PATH = os.environ.get("MM_HOSTCOPY_LIB") or os.path.join(os.path.dirname(_HERE), "libmm_hostcopy.so")
 _lib = None
 
 

@@ -1,0 +1,56 @@
+"""The oracle and the host-copy renderer under AddressSanitizer and
+UndefinedBehaviorSanitizer.
+
+Both C libraries are rebuilt here with -fsanitize=address,undefined (plus
+float-cast-overflow and float-divide-by-zero, which gcc's "undefined" leaves
+out), every finding fatal, and the oracle's pin tests and the host-copy tests
+run again in a child interpreter that loads those builds (MM_ORACLE_LIB,
+MM_HOSTCOPY_LIB) with the ASan runtime preloaded. The pins that compile
+cross-check programs of their own (ATen's and rocRAND's Philox) are left to
+the ordinary run. The served form's host scheduling policy has a sanitizer
+test of its own (test_sched_cpu.py)."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SAN = ["-fsanitize=address,undefined", "-fsanitize=float-cast-overflow",
+       "-fsanitize=float-divide-by-zero", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+       "-g", "-O1"]
+
+
+@pytest.mark.slow
+def test_oracle_and_hostcopy_pins_under_sanitizers(tmp_path):
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    asan = subprocess.run([gcc, "-print-file-name=libasan.so"], capture_output=True,
+                          text=True).stdout.strip()
+    if not os.path.isabs(asan) or not os.path.exists(asan):
+        pytest.skip("no ASan runtime")
+    oracle_lib = str(tmp_path / "liboracle_san.so")
+    subprocess.run([gcc, "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                    "-fexcess-precision=standard", "-fPIC", "-shared", "-Wall", "-Wextra", *SAN,
+                    os.path.join(ROOT, "oracle", "mm_oracle.c"), "-o", oracle_lib, "-lm"],
+                   check=True, capture_output=True, text=True)
+    hc = os.path.join(ROOT, "paper_2504_20937_amd", "hostcopy")
+    hostcopy_lib = str(tmp_path / "libmm_hostcopy_san.so")
+    subprocess.run([gcc, "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-fno-fast-math", "-Wall", *SAN, "-I", hc, os.path.join(hc, "hostcopy.c"),
+                    "-o", hostcopy_lib, "-lm"], check=True, capture_output=True, text=True)
+    env = dict(os.environ, MM_ORACLE_LIB=oracle_lib, MM_HOSTCOPY_LIB=hostcopy_lib,
+               LD_PRELOAD=asan, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    tests = [os.path.join(HERE, f) for f in ("test_oracle_displace.py", "test_oracle_render.py",
+                                              "test_oracle_edges.py", "test_oracle_philox.py",
+                                              "test_hostcopy_cpu.py")]
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-p", "no:cacheprovider",
+                        "-m", "not gpu", "-k", "not aten and not rocrand", *tests],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0, out[-4000:]
+    assert "passed" in r.stdout and "AddressSanitizer" not in out and "runtime error" not in out
