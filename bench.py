@@ -3,19 +3,21 @@
 Workload (default): 2^24 float3 points uniform in [0,1)^3 (seed 0), each
 frame displaces every point by a Philox draw of +-0.001 per coordinate, then
 splats it at 1920x1080 with a camera orbiting the cube centre (radius 2.5,
-fov 60 deg, 1 deg per frame), then resolves RGBA8. One hipGraph per frame.
-Positions start resident in HBM; nothing crosses PCIe in the timed region.
+fov 60 deg, 1 deg per frame), then resolves RGBA8. Eight frames per hipGraph
+launch, each with its own step and camera. Positions start resident in HBM;
+nothing crosses PCIe in the timed region.
 
 Prints ONE JSON line: throughput in Gpoints/s (value), frames/s, p50/p99
-frame time from HIP events on the frame stream before every timed frame and
-after the last, the roofline of the dominant kernel (the bin kernel, timed
-by events inside the frame graph on one frame in eight), the whole frame's
+frame time from the device clock stored by each timed frame's first kernel
+(and after the last), the roofline of the dominant kernel (the bin kernel,
+timed by events inside the frame graph on one frame in eight), the whole frame's
 roofline, the host it ran on, and the CPU oracle timed on a bounded sample
 of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
 import json
 import os
 import sys
@@ -46,7 +48,7 @@ TRAFFIC = {
                    "digest": "29266d046d1222ae", "fetch_kib": 98394.6, "write_kib": 335977.1,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
-PROFILE_EVERY = 8  # frames per profiled frame in the timed loop
+FRAMES_PER_LAUNCH = 8  # frames per graph launch (mm_step_render_frames)
 POINT_BYTES = 24   # float3 read + write per point and frame
 PIXEL_BYTES = 20   # key read + empty-key write (8 + 8) and RGBA8 write (4)
 
@@ -98,7 +100,11 @@ SETTLE_BLOCK = 64        # frames per host synchronisation while settling
 MAX_SETTLE_FRAMES = 20000
 
 
-def latency_fields(spans_ms, source: str = "timed frames") -> dict:
+FRAME_MARKS = "the device clock stored by each frame's first kernel as it starts, and after the last"
+
+
+def latency_fields(spans_ms, source: str = "timed frames",
+                   how: str = "HIP events on the frame stream before every frame and after the last") -> dict:
     """p50 / p99 of per-frame spans, one per frame; p99 is null with fewer
     than MIN_P99_SAMPLES frames, where it would be little more than the
     largest sample."""
@@ -108,8 +114,7 @@ def latency_fields(spans_ms, source: str = "timed frames") -> dict:
                              else None),
             "max_frame_ms": float(spans.max()) if spans.size else None,
             "latency_samples": int(spans.size),
-            "latency_source": f"{source}: HIP events on the frame stream before every frame "
-                              f"and after the last"}
+            "latency_source": f"{source}: {how}"}
 
 
 def make_points(n: int, dist: str) -> np.ndarray:
@@ -658,6 +663,8 @@ def main() -> int:
     ap.add_argument("--cull", choices=["auto", "on", "off"], default="auto",
                     help="frame: the occlusion cull of the binned 3D 1x1 pass (auto: where it applies)")
     ap.add_argument("--autotune", action="store_true", help="time the shapes, keep the fastest")
+    ap.add_argument("--frames-per-launch", type=int, default=FRAMES_PER_LAUNCH,
+                    help="frames per graph launch (1: one mm_step_render call per frame)")
     ap.add_argument("--palette", action="store_true",
                     help="frame: colour through a 256-entry palette and 1-byte indices (mm_set_colour)")
     ap.add_argument("--overlap", action="store_true",
@@ -756,45 +763,52 @@ def main() -> int:
         mm.mm_set_frame_overlap(view, True)
     print(f"bench: {n} points, {w}x{h}, warmup {W}, timed {K}, splat {mode} {tuning}",
           file=sys.stderr, flush=True)
+    # Frames go B = --frames-per-launch to a graph launch (mm_step_render_frames:
+    # each frame its own step and camera, the same frames as B single calls)
+    B = max(1, min(64, args.frames_per_launch))
+    L = mm.lib()
+
+    def cameras(first, count):
+        return np.ascontiguousarray(
+            np.stack([frame_camera(args.dist, first + k, w, h) for k in range(count)]),
+            dtype=np.float32).reshape(-1)
+
+    def frames(cam_all, first, count, what):
+        # cam_all: count * 16 floats; the C entry point directly, so Python
+        # adds as little as possible to the host side of a launch
+        for k0 in range(0, count, B):
+            c = min(B, count - k0)
+            ptr = C.cast(cam_all.ctypes.data + 64 * k0, C.POINTER(C.c_float))
+            st = L.mm_step_render_frames(view, first + k0, c, ptr)
+            if st:
+                raise mm.MMError(st, what, mm.mm_last_error())
+
     # W warm-up frames as asked, then further untimed frames of the same loop
     # until SETTLE_S seconds of them have run back to back: a few frames after
     # set-up still run at a lower rate (about 17% at 2^24 points, 1080p) until
     # the device settles under sustained load
-    f, t_settle = 0, time.perf_counter()
-    while f < W or (time.perf_counter() - t_settle < SETTLE_S and f < W + MAX_SETTLE_FRAMES):
-        for _ in range(SETTLE_BLOCK):
-            mm.mm_set_camera(view, frame_camera(args.dist, f, w, h))
-            mm.mm_step_render(view, f)
-            f += 1
-            if f == W:
-                break
+    frames(cameras(0, W), 0, W, "warm-up")
+    torch.cuda.synchronize()
+    f, t_settle = W, time.perf_counter()
+    while time.perf_counter() - t_settle < SETTLE_S and f < W + MAX_SETTLE_FRAMES:
+        frames(cameras(f, SETTLE_BLOCK), f, SETTLE_BLOCK, "settle")
+        f += SETTLE_BLOCK
         torch.cuda.synchronize()
-        if f == W:
-            t_settle = time.perf_counter()
     F0, settle_frames = f, f - W
-    # HIP events inside the frame graph on one frame in PROFILE_EVERY: the
-    # host calls that re-point a timed graph's event nodes would otherwise
-    # pace the frame loop
-    mm.mm_profile_every(view, PROFILE_EVERY)
-    prof_cap = (K + PROFILE_EVERY - 1) // PROFILE_EVERY
-    # the loop calls the C entry points directly with the cameras converted
-    # before the timed region (they are inputs, like the points), so Python
-    # adds as little as possible to the host side of a frame; each frame still
-    # hands its camera to mm_set_camera, and each call's status is checked
-    L = mm.lib()
-    cam_arrs = [np.ascontiguousarray(frame_camera(args.dist, F0 + k, w, h), dtype=np.float32).reshape(16)
-                for k in range(K)]
-    cam_ptrs = [mm._fptr(a) for a in cam_arrs]  # cam_arrs keeps the memory alive
+    # HIP events inside the frame graph on the first frame of every launch
+    # (1 in B frames): the kernel durations of the roofline
+    mm.mm_profile_every(view, B)
+    prof_cap = (K + B - 1) // B
+    # the cameras of the timed frames are inputs, like the points: converted
+    # before the timed region
+    cam_all = cameras(F0, K)
     mm.mm_profile_begin(view, prof_cap)  # synchronises
-    # one event before every frame and one after the last (outside the frame
-    # graph): the per-frame spans for p50 / p99
+    # the device clock at the start of every frame (stored by its first
+    # kernel) and after the last: the per-frame spans for p50 / p99
     mm.mm_mark_begin(view, K + 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(K):
-        st = L.mm_set_camera(view, cam_ptrs[k]) or L.mm_step_render(view, F0 + k)
-        if st:
-            raise mm.MMError(st, "frame loop", mm.mm_last_error())
+    frames(cam_all, F0, K, "frame loop")
     # with overlap, the last frame is drawn inside the timed region; the
     # closing mark follows it
     mm.mm_mark_end(view)
@@ -809,14 +823,9 @@ def main() -> int:
     lat_spans, lat_source = frame_spans, "timed frames"
     if K < MIN_P99_SAMPLES:
         R = LATENCY_FRAMES
-        lat_cams = [np.ascontiguousarray(frame_camera(args.dist, F0 + K + k, w, h),
-                                         dtype=np.float32).reshape(16) for k in range(R)]
-        lat_ptrs = [mm._fptr(a) for a in lat_cams]
+        lat_cams = cameras(F0 + K, R)
         mm.mm_mark_begin(view, R + 1)
-        for k in range(R):
-            st = L.mm_set_camera(view, lat_ptrs[k]) or L.mm_step_render(view, F0 + K + k)
-            if st:
-                raise mm.MMError(st, "latency loop", mm.mm_last_error())
+        frames(lat_cams, F0 + K, R, "latency loop")
         mm.mm_mark_end(view)
         lat_spans = mm.mm_mark_read(view, R + 1)
         lat_source = f"a latency run of {R} frames after the {K} timed ones"
@@ -850,16 +859,17 @@ def main() -> int:
                    "points": n, "width": w, "height": h, "footprint": args.footprint,
                    "amplitude": amp, "wrap": wrap,
                    "graph": ("bin of frame f beside the draw of frame f - 1 (two streams)"
-                             if args.overlap else "one hipGraph per frame"),
+                             if args.overlap else f"{B} frames per hipGraph launch"),
                    "colour": "256-entry palette, 1-byte indices" if args.palette else "index hash",
                    "splat": mode, "tile": tuning[1], "points_per_thread": tuning[2],
                    "splits": tuning[3], "bin_threads": tuning[4], "piece_records": tuning[5],
-                   "occlusion_cull": "on" if tuning[6] == mm.MM_CULL_ON else "off"},
+                   "occlusion_cull": "on" if tuning[6] == mm.MM_CULL_ON else "off",
+                   "frames_per_launch": 1 if args.overlap else B},
         "frames_per_s": K / elapsed,
-        **latency_fields(lat_spans, lat_source),
+        **latency_fields(lat_spans, lat_source, FRAME_MARKS),
         "timed_frames_p50_ms": float(np.percentile(frame_spans, 50)),
         "timed_frames_max_ms": float(np.max(frame_spans)),
-        "kernel_profiled_frames": f"{len(frame_ms)} (1 in {PROFILE_EVERY} of the timed frames)",
+        "kernel_profiled_frames": f"{len(frame_ms)} (1 in {B} of the timed frames)",
         "graph_ms_profiled_mean": float(np.mean(frame_ms)),
         "point_kernel_ms": splat_avg,
         "rest_of_frame_ms": float(np.mean(resolve_ms)),

@@ -160,6 +160,20 @@ mm_status mm_render(mm_view view);
  * launch on the stream. Equivalent to mm_step then mm_render. */
 mm_status mm_step_render(mm_view view, uint32_t step);
 
+/* `count` frames in one graph launch (1 <= count <= 64): frame i displaces
+ * with step first_step + i and, when view_proj is not NULL, renders with the
+ * camera view_proj[16 i .. 16 i + 15] (row-major, count * 16 floats; NULL:
+ * the view's camera for every frame). The same frames as mm_set_camera then
+ * mm_step_render per frame, bit for bit, without the gap a device leaves
+ * between graph launches (section "Performance Benchmark" runs its time
+ * steps back to back); the frame buffer holds the last one, and the view's
+ * camera is left at the last camera. With frame overlap the frames are
+ * enqueued one by one. Frame marks mark every frame; a profile samples at
+ * most the first frame of a launch. The first call for a count builds and
+ * keeps that count's graph. */
+mm_status mm_step_render_frames(mm_view view, uint32_t first_step, uint32_t count,
+                                const float* view_proj);
+
 /* Colour of a view's points (section "Views": a colour property read per
  * element, or through an index description into a table, as value mapping
  * with a colormap; a default when the property is absent). */
@@ -320,16 +334,17 @@ mm_status mm_profile_end(mm_view view, float* splat_ms, float* resolve_ms, float
 
 /* Frame marks, for the latency of every frame of a loop: from
  * mm_mark_begin on, each of the next `capacity` calls of mm_step_render
- * records one HIP event on the instance's stream just before it enqueues its
- * frame (outside the frame graph, so every frame launches the same graph).
- * mm_mark_end stops marking; if marks are left it records one more after
- * the last frame (drawing a pending overlapped frame first). It does not
- * wait. mm_mark_read waits for the last mark and writes to interval_ms (an
- * array of `capacity` - 1; may be NULL) the time between consecutive marks:
- * frame k's span on the device, from the point its stream reached frame k
- * to the point it reached the next mark, idle gaps included, and to *count
- * the number of intervals. A loop of K frames takes capacity K + 1.
- * 2 <= capacity <= 2^20. */
+ * marks its frame: the frame's first kernel stores the device's constant-rate
+ * clock (wall_clock64) as it starts, from inside the frame graph, so a mark
+ * adds no work to the stream between frames. mm_mark_end stops marking; if
+ * marks are left it enqueues one more after the last frame (drawing a
+ * pending overlapped frame first). It does not wait. mm_mark_read waits for
+ * the stream and writes to interval_ms (an array of `capacity` - 1; may be
+ * NULL) the time between consecutive marks: frame k's span on the device,
+ * from the start of frame k to the start of the next frame (or the closing
+ * mark), idle gaps included, and to *count the number of intervals;
+ * MM_ERR_HIP if a mark was not written. A loop of K frames takes capacity
+ * K + 1. 2 <= capacity <= 2^20. */
 mm_status mm_mark_begin(mm_view view, uint32_t capacity);
 mm_status mm_mark_end(mm_view view);
 mm_status mm_mark_read(mm_view view, float* interval_ms, uint32_t* count);

@@ -201,6 +201,7 @@ def _declare(L):
         "mm_step": ([_vp, C.c_uint32], _status),
         "mm_render": ([_vp], _status),
         "mm_step_render": ([_vp, C.c_uint32], _status),
+        "mm_step_render_frames": ([_vp, C.c_uint32, C.c_uint32, C.POINTER(C.c_float)], _status),
         "mm_set_frame_overlap": ([_vp, C.c_uint32], _status),
         "mm_set_colour": ([_vp, C.POINTER(mm_colour_desc)], _status),
         "mm_create_grid": ([_vp, C.POINTER(mm_grid_desc), C.POINTER(_vp)], _status),
@@ -412,6 +413,18 @@ def mm_step(view: int, step: int) -> None:
 
 def mm_render(view: int) -> None:
     _check(lib().mm_render(view), "mm_render")
+
+
+def mm_step_render_frames(view: int, first_step: int, count: int, cameras=None) -> None:
+    """`count` frames (steps first_step ..) in one graph launch; cameras: None
+    or `count` 4x4 row-major matrices."""
+    if cameras is None:
+        _check(lib().mm_step_render_frames(view, first_step, count, None), "mm_step_render_frames")
+        return
+    m = np.ascontiguousarray(np.asarray(cameras, dtype=np.float32).reshape(-1))
+    if m.size != 16 * count:
+        raise ValueError(f"{count} frames need {16 * count} camera floats, got {m.size}")
+    _check(lib().mm_step_render_frames(view, first_step, count, _fptr(m)), "mm_step_render_frames")
 
 
 def mm_step_render(view: int, step: int) -> None:

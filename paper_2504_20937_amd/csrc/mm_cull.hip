@@ -56,6 +56,7 @@ __global__ __launch_bounds__(kHintThreads) void hint_kernel(BinArgs a) {
     __shared__ uint32_t bm[9][BMW];             // per destination tile d = (dy + 1) * 3 + dx + 1
     __shared__ uint32_t bmax[9][NBLK];
     const uint32_t t = blockIdx.x;
+    if (t == 0 && threadIdx.x == 0 && a.mark) *a.mark = wall_clock64();  // the frame's first kernel
     if (t >= a.v.ntiles) return;
     if (load_flag(&a.v.active[t]) != a.stamp - 1u) return;  // not drawn in the previous frame
     const uint32_t tid = threadIdx.x;

@@ -36,6 +36,8 @@ struct PointArgs {
     CloudArgs c;
     ViewGeom g;
     uint64_t* depth;    // width * height keys
+    uint64_t* mark;     // frame mark: the device clock when the frame's first
+                        // kernel starts (nullptr: none)
 };
 
 // Colour source of a view: the per-point hash (table == nullptr), or RGBA8
@@ -129,6 +131,8 @@ struct BinArgs {
     uint32_t* stamp_out; // the frame stamp, for the tile, merge and seam passes
     uint32_t stamp;
     uint32_t shift;      // tile side = 1 << shift
+    uint64_t* mark;      // frame mark, as PointArgs (stored by the occlusion hint
+                         // kernel when it runs first, else by the bin kernel)
 };
 
 struct TileArgs {
@@ -190,6 +194,8 @@ hipError_t launch_point(const PointArgs& a, int dim, int footprint, bool wrap, P
                         hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_fill(uint64_t* keys, uint64_t nkeys, uint64_t value, hipStream_t s);
+// Stores the device clock (wall_clock64) at *slot when the stream reaches it.
+hipError_t launch_mark(uint64_t* slot, hipStream_t s);
 // Copies `bytes` from pinned, host-coherent memory (src: its device address,
 // 8-byte aligned) to device memory (dst, 8-byte aligned) with a kernel in
 // stream order: no switch to a copy engine between the kernels around it.

@@ -24,6 +24,7 @@ using namespace dev;
 template <int DIM, int FOOT, bool WRAP, int PHASE>
 __global__ __launch_bounds__(256) void point_kernel(PointArgs a) {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i == 0 && a.mark) *a.mark = wall_clock64();
     if (i >= a.c.n) return;
     float x, y, z;
     load_point<DIM>(a.c.pos, i, x, y, z);
@@ -153,6 +154,15 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
     const dim3 grid(static_cast<uint32_t>(std::min<uint64_t>((n8 + 255) / 256, 64)) + (n8 == 0 ? 1u : 0u));
     void* args[] = {&src8, &dst8, &n8, &src_tail, &dst_tail, &tail};
     return hipLaunchKernel(reinterpret_cast<const void*>(&upload_kernel), grid, dim3(256), args, 0, s);
+}
+
+__global__ __launch_bounds__(64) void mark_kernel(uint64_t* slot) {
+    if (threadIdx.x == 0) *slot = wall_clock64();
+}
+
+hipError_t launch_mark(uint64_t* slot, hipStream_t s) {
+    void* args[] = {&slot};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&mark_kernel), dim3(1), dim3(64), args, 0, s);
 }
 
 hipError_t launch_fill(uint64_t* keys, uint64_t nkeys, uint64_t value, hipStream_t s) {

@@ -36,6 +36,20 @@ struct FrameGraph {
     hipGraphNode_t ev[kFrameEvents] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+// Most frames one graph launch takes (mm_step_render_frames).
+constexpr uint32_t kMaxGraphFrames = 64;
+
+// Several frames in one graph: the frame's kernels `frames` times in a chain;
+// the first frame carries the timed graph's event nodes, pointed at spare
+// events when that frame is not profiled.
+struct MultiGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t frames = 0;
+    std::vector<hipGraphNode_t> per_frame;  // frame f, per-frame node j: f * frame_nodes + j
+    hipGraphNode_t ev[kFrameEvents] = {nullptr, nullptr, nullptr, nullptr};
+};
+
 }  // namespace
 
 struct mm_view_s {
@@ -79,12 +93,15 @@ struct mm_view_s {
     std::vector<mm::Launch> nodes;
     uint32_t frame_nodes = 1;
     FrameGraph plain, timed;
+    MultiGraph multi;
+    hipEvent_t spare[kFrameEvents] = {nullptr, nullptr, nullptr, nullptr};  // unprofiled multi frames
     std::vector<hipEvent_t> events;  // kFrameEvents per profiled frame
     uint32_t prof_cap = 0, prof_count = 0;
     uint32_t prof_every = 1, prof_skip = 0;  // record 1 frame in prof_every
     bool profiling = false;
-    // frame marks: one event before each frame, one after the last
-    std::vector<hipEvent_t> marks;
+    // frame marks: the device clock when each frame's first kernel starts, and
+    // one more after the last frame (mark_cap slots)
+    uint64_t* mark_ring = nullptr;
     uint32_t mark_cap = 0, mark_count = 0;
     bool marking = false;
     // Frame overlap (binned only): frame f is binned into record set f & 1 on
@@ -131,6 +148,12 @@ void destroy_graph(FrameGraph& fg) {
     fg = FrameGraph{};
 }
 
+void destroy_multi(MultiGraph& mg) {
+    if (mg.exec) (void)hipGraphExecDestroy(mg.exec);
+    if (mg.graph) (void)hipGraphDestroy(mg.graph);
+    mg = MultiGraph{};
+}
+
 // The frame graph: the kernels of v->nodes in a chain; with timed set,
 // event-record nodes go before the first kernel, before and after the point
 // pass, and at the end.
@@ -164,6 +187,46 @@ mm_status build_graph(mm_view v, bool timed, FrameGraph& out) {
         return fail(MM_ERR_HIP, "building the frame graph failed: %s", hipGetErrorString(err));
     }
     out = fg;
+    return MM_OK;
+}
+
+// `frames` frames of v->nodes in one chain (MultiGraph).
+mm_status build_multi(mm_view v, uint32_t frames, MultiGraph& out) {
+    for (hipEvent_t& e : v->spare)
+        if (!e) MM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    MultiGraph mg;
+    MM_HIP(hipGraphCreate(&mg.graph, 0));
+    mg.per_frame.assign(static_cast<size_t>(frames) * v->frame_nodes, nullptr);
+    hipError_t err = hipSuccess;
+    hipGraphNode_t prev = nullptr;
+    auto add_event = [&](int j) {
+        if (err != hipSuccess) return;
+        err = hipGraphAddEventRecordNode(&mg.ev[j], mg.graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                         v->spare[j]);
+        prev = mg.ev[j];
+    };
+    const size_t point = v->frame_nodes - 1;
+    for (uint32_t f = 0; f < frames && err == hipSuccess; ++f) {
+        if (f == 0) add_event(0);
+        for (size_t k = 0; k < v->nodes.size() && err == hipSuccess; ++k) {
+            if (f == 0 && k == point) add_event(1);
+            void* args[] = {node_arg(v, k)};
+            hipKernelNodeParams p = node_params(v->nodes[k], args);
+            hipGraphNode_t n = nullptr;
+            err = hipGraphAddKernelNode(&n, mg.graph, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+            if (k < v->frame_nodes) mg.per_frame[static_cast<size_t>(f) * v->frame_nodes + k] = n;
+            prev = n;
+            if (f == 0 && k == point) add_event(2);
+        }
+        if (f == 0) add_event(3);
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&mg.exec, mg.graph, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        destroy_multi(mg);
+        return fail(MM_ERR_HIP, "building the %u-frame graph failed: %s", frames, hipGetErrorString(err));
+    }
+    mg.frames = frames;
+    out = std::move(mg);
     return MM_OK;
 }
 
@@ -475,25 +538,29 @@ void teardown_splat(mm_view v) {
     if (v->rstream) (void)hipStreamSynchronize(v->rstream);
     destroy_graph(v->plain);
     destroy_graph(v->timed);
+    destroy_multi(v->multi);
     v->profiling = false;
     free_splat_buffers(v);
 }
 
-// Records the next frame mark on the instance stream, while marks are left.
-mm_status record_mark(mm_view v) {
-    if (!v->marking || v->mark_count >= v->mark_cap) return MM_OK;
-    MM_HIP(hipEventRecord(v->marks[v->mark_count], v->inst->stream));
-    v->mark_count++;
-    return MM_OK;
+// The slot of the next frame mark while marks are left (the frame's first
+// kernel stores the clock there), else nullptr.
+uint64_t* take_mark(mm_view v) {
+    if (!v->marking || v->mark_count >= v->mark_cap) return nullptr;
+    return v->mark_ring + v->mark_count++;
 }
 
 void destroy_view_resources(mm_view v) {
     teardown_splat(v);
+    for (hipEvent_t& e : v->spare) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     destroy_overlap(v);
     for (hipEvent_t e : v->events) (void)hipEventDestroy(e);
     v->events.clear();
-    for (hipEvent_t e : v->marks) (void)hipEventDestroy(e);
-    v->marks.clear();
+    if (v->mark_ring) (void)hipFree(v->mark_ring);
+    v->mark_ring = nullptr;
     v->marking = false;
     if (v->colour) (void)hipFree(v->colour);
     v->colour = nullptr;
@@ -568,10 +635,10 @@ mm_status flush_frame(mm_view v) {
 // bin kernel (instance stream) and after the draw (render stream).
 mm_status overlap_frame(mm_view v, mm::Phase phase, uint32_t step) {
     MM_TRY(next_stamp(v));
-    MM_TRY(record_mark(v));
     const int k = static_cast<int>(v->stamp & 1u);
-    mm::BinArgs& b = set_bin(v, k);
+    mm::BinArgs b = set_bin(v, k);
     b.c.step = step;
+    b.mark = take_mark(v);
     hipStream_t s = v->inst->stream;
     // the last draw of set k has read its records
     MM_HIP(hipStreamWaitEvent(s, v->ev_drawn[k], 0));
@@ -1065,6 +1132,7 @@ mm_status mm_render(mm_view v) {
                                         v->tuning.bin_threads, v->args.c.n, v->ntiles);
     mm::BinArgs ba = v->bargs;
     ba.v.cull = nullptr;
+    ba.mark = nullptr;
     void* bargs[] = {&ba};
     MM_HIP(hipLaunchKernel(b.func, b.grid, b.block, bargs, b.shared, s));
     for (size_t k = v->frame_nodes; k < v->nodes.size(); ++k) {
@@ -1079,17 +1147,23 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
     MM_TRY(require_ready(v, "step_render"));
     DeviceGuard guard(v->inst->device);
     if (v->overlap) return overlap_frame(v, mm::kDisplaceRender, step);
+    // per-frame arguments: copies, so that no other launch takes the mark
+    mm::BinArgs ba;
+    mm::PointArgs pa;
     void* first_arg;
     if (binned(v)) {
         MM_TRY(next_stamp(v));
-        v->bargs.c.step = step;
-        first_arg = &v->bargs;
+        ba = v->bargs;
+        ba.c.step = step;
+        ba.mark = take_mark(v);
+        first_arg = &ba;
     } else {
-        v->args.c.step = step;
-        first_arg = &v->args;
+        pa = v->args;
+        pa.c.step = step;
+        pa.mark = take_mark(v);
+        first_arg = &pa;
     }
     void* args[] = {first_arg};
-    MM_TRY(record_mark(v));
     FrameGraph* fg = &v->plain;
     if (v->profiling && v->prof_count < v->prof_cap && v->prof_skip++ % v->prof_every == 0) {
         const uint32_t k = v->prof_count++;
@@ -1104,6 +1178,76 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
         MM_HIP(hipGraphExecKernelNodeSetParams(fg->exec, fg->per_frame[j], &pp));
     }
     MM_HIP(hipGraphLaunch(fg->exec, v->inst->stream));
+    return MM_OK;
+}
+
+mm_status mm_step_render_frames(mm_view v, uint32_t first_step, uint32_t count, const float* view_proj) {
+    MM_TRY(require_ready(v, "step_render_frames"));
+    if (count < 1 || count > kMaxGraphFrames)
+        return fail(MM_ERR_INVALID_ARG, "step_render_frames: count %u outside [1, %u]", count, kMaxGraphFrames);
+    if (view_proj)
+        for (uint64_t k = 0; k < 16ull * count; ++k)
+            if (!std::isfinite(view_proj[k]))
+                return fail(MM_ERR_INVALID_ARG, "step_render_frames: view_proj[%llu] is not finite",
+                            (unsigned long long)k);
+    DeviceGuard guard(v->inst->device);
+    if (v->overlap || count == 1) {  // frame by frame, as the same calls one at a time
+        for (uint32_t i = 0; i < count; ++i) {
+            if (view_proj) MM_TRY(mm_set_camera(v, view_proj + 16ull * i));
+            MM_TRY(mm_step_render(v, first_step + i));
+        }
+        return MM_OK;
+    }
+    if (v->multi.frames != count) {
+        destroy_multi(v->multi);
+        MM_TRY(build_multi(v, count, v->multi));
+    }
+    // stamps of the whole launch without a wrap in between (a wrap clears
+    // the tile flags on the stream, which must come before the launch)
+    if (binned(v) && v->stamp > 0xFFFFFFFFu - count) {
+        MM_HIP(hipMemsetAsync(v->active, 0, (static_cast<size_t>(v->ntiles) + 1) * 4, v->inst->stream));
+        v->stamp = 0;
+    }
+    MultiGraph& mg = v->multi;
+    bool profiled = false;
+    for (uint32_t i = 0; i < count; ++i) {
+        mm::BinArgs ba;
+        mm::PointArgs pa;
+        void* first_arg;
+        if (binned(v)) {
+            MM_TRY(next_stamp(v));
+            ba = v->bargs;
+            ba.c.step = first_step + i;
+            if (view_proj) set_camera_rows(ba.v.g, view_proj + 16ull * i);
+            ba.mark = take_mark(v);
+            first_arg = &ba;
+        } else {
+            pa = v->args;
+            pa.c.step = first_step + i;
+            if (view_proj) set_camera_rows(pa.g, view_proj + 16ull * i);
+            pa.mark = take_mark(v);
+            first_arg = &pa;
+        }
+        void* args[] = {first_arg};
+        for (uint32_t j = 0; j < v->frame_nodes; ++j) {
+            hipKernelNodeParams pp = node_params(v->nodes[j], args);
+            MM_HIP(hipGraphExecKernelNodeSetParams(mg.exec, mg.per_frame[static_cast<size_t>(i) * v->frame_nodes + j],
+                                                   &pp));
+        }
+        // the profile samples the first frame of a launch (the one with events)
+        if (v->profiling && v->prof_count < v->prof_cap && v->prof_skip++ % v->prof_every == 0 && i == 0) {
+            const uint32_t k = v->prof_count++;
+            for (int j = 0; j < kFrameEvents; ++j)
+                MM_HIP(hipGraphExecEventRecordNodeSetEvent(mg.exec, mg.ev[j],
+                                                           v->events[static_cast<size_t>(kFrameEvents) * k + j]));
+            profiled = true;
+        }
+    }
+    if (!profiled)
+        for (int j = 0; j < kFrameEvents; ++j)
+            MM_HIP(hipGraphExecEventRecordNodeSetEvent(mg.exec, mg.ev[j], v->spare[j]));
+    MM_HIP(hipGraphLaunch(mg.exec, v->inst->stream));
+    if (view_proj) MM_TRY(mm_set_camera(v, view_proj + 16ull * (count - 1)));
     return MM_OK;
 }
 
@@ -1274,11 +1418,12 @@ mm_status mm_mark_begin(mm_view v, uint32_t capacity) {
         return fail(MM_ERR_INVALID_ARG, "mark_begin: capacity outside [2, 2^20]");
     DeviceGuard guard(v->inst->device);
     MM_HIP(hipStreamSynchronize(v->inst->stream));
-    for (hipEvent_t e : v->marks) (void)hipEventDestroy(e);
-    v->marks.assign(capacity, nullptr);
     v->marking = false;
-    // timing only: no system-scope fence per mark
-    for (auto& e : v->marks) MM_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    if (v->mark_ring) (void)hipFree(v->mark_ring);
+    v->mark_ring = nullptr;
+    MM_HIP(dev_malloc(reinterpret_cast<void**>(&v->mark_ring), sizeof(uint64_t) * capacity));
+    // a slot no frame wrote reads 0 (refused by mm_mark_read)
+    MM_HIP(hipMemsetAsync(v->mark_ring, 0, sizeof(uint64_t) * capacity, v->inst->stream));
     v->mark_cap = capacity;
     v->mark_count = 0;
     v->marking = true;
@@ -1291,7 +1436,7 @@ mm_status mm_mark_end(mm_view v) {
     DeviceGuard guard(v->inst->device);
     if (v->mark_count < v->mark_cap) {  // close the last marked frame
         MM_TRY(flush_frame(v));
-        MM_HIP(hipEventRecord(v->marks[v->mark_count++], v->inst->stream));
+        MM_HIP(mm::launch_mark(v->mark_ring + v->mark_count++, v->inst->stream));
     }
     v->marking = false;
     return MM_OK;
@@ -1303,12 +1448,18 @@ mm_status mm_mark_read(mm_view v, float* interval_ms, uint32_t* count) {
     const uint32_t marks = v->mark_count;
     if (marks < 2) return fail(MM_ERR_INVALID_ARG, "mark_read: fewer than two marks");
     DeviceGuard guard(v->inst->device);
-    MM_HIP(hipEventSynchronize(v->marks[marks - 1]));
-    for (uint32_t k = 0; k + 1 < marks; ++k) {
-        float t = 0.0f;
-        MM_HIP(hipEventElapsedTime(&t, v->marks[k], v->marks[k + 1]));
-        if (interval_ms) interval_ms[k] = t;
-    }
+    int khz = 0;  // the device clock's rate
+    MM_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, v->inst->device));
+    if (khz <= 0) return fail(MM_ERR_HIP, "mark_read: device clock rate %d kHz", khz);
+    MM_HIP(hipStreamSynchronize(v->inst->stream));
+    std::vector<uint64_t> t(marks);
+    MM_HIP(hipMemcpy(t.data(), v->mark_ring, sizeof(uint64_t) * marks, hipMemcpyDeviceToHost));
+    for (uint32_t k = 0; k < marks; ++k)
+        if (t[k] == 0 || (k > 0 && t[k] < t[k - 1]))
+            return fail(MM_ERR_HIP, "mark_read: mark %u was not written in order", k);
+    if (interval_ms)
+        for (uint32_t k = 0; k + 1 < marks; ++k)
+            interval_ms[k] = static_cast<float>(static_cast<double>(t[k + 1] - t[k]) / khz);
     *count = marks - 1;
     return MM_OK;
 }

@@ -205,9 +205,16 @@ __device__ __forceinline__ void splat_segment(const uint64_t* seg, uint64_t* key
             const uint64_t next = uniform_u64(mine, u + 1u);
             k += static_cast<uint32_t>(__popcll(after)) + static_cast<uint32_t>(next & 1ull);
         }
+        if (w0 + 64u * U <= r1) {
+            // whole windows (all but a range's last batch): no lane is past
+            // the range, so no branch keeps a load from issuing with the others
 #pragma unroll
-        for (uint32_t u = 0; u < U; ++u)
-            if (w0 + 64u * u + lane < r1) splat_record<S>(keys, r[u], gb[u]);
+            for (uint32_t u = 0; u < U; ++u) splat_record<S>(keys, r[u], gb[u]);
+        } else {
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (w0 + 64u * u + lane < r1) splat_record<S>(keys, r[u], gb[u]);
+        }
     }
 }
 

@@ -101,6 +101,21 @@ def test_3d_uniform_ragged_small(rig, mode):
          lambda s: synth.orbit_camera(s, 320, 240), mode=mode)
 
 
+# 1x1 footprint with several static splits per tile (a merge pass resolves)
+PART_SHAPES = [(2, 32, 8, 8, 1024, ST), (2, 16, 8, 4, 512, ST), (2, 64, 8, 2, 1024, ST),
+               (2, 32, 4, 8, 256, ST)]
+
+
+@pytest.mark.parametrize("mode", PART_SHAPES, ids=_ids(PART_SHAPES))
+def test_3d_dense_tiles_in_splits(rig, mode):
+    """Clustered points give tiles of 10^4 records and more, shared by the
+    splits; the camera jumps every third frame, so tiles appear and leave."""
+    say(f"case: 3D mixture, 2^18 points, 640x360, 1x1 in splits, 9 frames, jumping camera, mode {mode}")
+    pts = synth.gaussian_mixture(1 << 18, seed=7)
+    _run(rig, pts, 3, 640, 360, 1, 7, 0.001, False, 9,
+         lambda s: synth.orbit_camera(70 * (s // 3), 640, 360), mode=mode)
+
+
 @pytest.mark.parametrize("mode", MODES, ids=_ids(MODES))
 def test_3d_split_step_render_matches(rig, mode):
     say("case: 3D uniform, mm_step + mm_render, 30001 points, 200x100, 5 frames")
@@ -504,6 +519,47 @@ def test_frame_marks_time_every_frame(rig, mode):
     assert iv.sum() >= fr[:3].sum() * 0.99
     assert np.array_equal(mm.mm_read_frame(view, 640, 480), want)
     assert same_bits(rig.positions(dev), ref)
+
+
+@pytest.mark.parametrize("mode", [DIRECT, (2, 32, 8, 1, 1024, ST), (2, 16, 4, 2, 256, ST),
+                                  (2, 32, 16, 1, 512, ST, CULL_ON)],
+                         ids=["direct", "binned-fused", "binned-z2", "binned-cull"])
+def test_step_render_frames_matches_the_oracle(rig, mode):
+    """Several frames per graph launch: after each launch the frame buffer and
+    the positions equal the oracle's after the same steps and cameras (tiles
+    left by the cloud between frames of one launch are cleared), for counts
+    1, 7, 16 and 3, with per-frame cameras and with the view's own; frame
+    marks cover every frame of every launch."""
+    say(f"case: mm_step_render_frames, 100003 points, 320x240, mode {mode}")
+    mm = rig.mm
+    n, w, h, seed, amp = 100003, 320, 240, 11, 0.002
+    pts = synth.uniform_cube(n, seed=seed)
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, n, 3, w, h, 1, seed, amp, False, synth.orbit_camera(0, w, h))
+    mm.mm_set_tuning(view, *mode)
+    ref, step, cam = pts.copy(), 0, synth.orbit_camera(0, w, h)
+    plan = [(7, True), (1, True), (16, False), (3, True)]
+    total = sum(c for c, _ in plan)
+    mm.mm_mark_begin(view, total + 1)
+    for count, with_cams in plan:
+        cams = [synth.orbit_camera(13 * (step + i), w, h) for i in range(count)] if with_cams else None
+        mm.mm_step_render_frames(view, step, count, cams)
+        for i in range(count):
+            oracle.displace(ref, seed, step + i, amp, False)
+        if with_cams:
+            cam = cams[-1]
+        want = oracle.render(ref, seed, cam, w, h, 1)
+        got = mm.mm_read_frame(view, w, h)
+        assert np.array_equal(got, want), f"after steps {step}..{step + count - 1}: {first_diff(got, want)}"
+        assert same_bits(rig.positions(dev), ref), f"positions after step {step + count - 1}"
+        step += count
+    mm.mm_mark_end(view)
+    iv = mm.mm_mark_read(view, total + 1)
+    assert iv.shape == (total,) and np.all(iv > 0), iv
+    with pytest.raises(mm.MMError):
+        mm.mm_step_render_frames(view, 0, 65, None)
+    with pytest.raises(mm.MMError):
+        mm.mm_step_render_frames(view, 0, 0, None)
 
 
 def test_invalid_descriptions_are_rejected(rig):
