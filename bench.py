@@ -34,7 +34,7 @@ CSRC = os.path.join(ROOT, "paper_2504_20937_amd", "csrc")
 
 # HBM traffic of the dominant kernel per launch, from rocprofv3 --pmc runs of
 # this benchmark's default workload (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch), scaled by what the same counters read for a plain 256 MiB device
+# dispatch, mean of the last 25 dispatches), scaled by what the same counters read for a plain 256 MiB device
 # copy (FETCH_SIZE reads half the copied bytes: x2; WRITE_SIZE reads them
 # all: x1). Keyed by a digest of the sources the kernel is built from: any
 # change to them makes the entry stale and the reported traffic null until it
@@ -45,7 +45,7 @@ KERNEL_SOURCES = {
 TRAFFIC = {
     "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
                    "tuning": [2, 32, 8, 1, 1024, 0xFFFFFFFF, 2],
-                   "digest": "29266d046d1222ae", "fetch_kib": 98394.6, "write_kib": 335977.1,
+                   "digest": "94b7f6d8371b4f5e", "fetch_kib": 98395.0, "write_kib": 335980.7,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 FRAMES_PER_LAUNCH = 8  # frames per graph launch (mm_step_render_frames)
