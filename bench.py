@@ -392,6 +392,75 @@ def bench_served(args) -> dict:
                 "launches": st["launches"], "mean_batch": count / max(1, st["launches"]),
                 "evictions": st["evictions"], "admissions": st["admissions"]}
 
+    def served_vs_batched(rounds):
+        """One request set run both ways from the same initial positions:
+        session c renders cloud c at screen SERVED_SCREENS[c % 3], and round r
+        asks every cloud for its frame at step r with the orbit camera of
+        frame r (the clouds' start angles). Served: every request submitted
+        at once (saturation). Batched offline: one batch of the 64 (cloud,
+        screen) views, one batch frame per round. The last frame of every
+        session is compared between the two (bit for bit)."""
+        nc = len(specs)
+        scr = [SERVED_SCREENS[c % 3] for c in range(nc)]
+        start = [float(specs[c].views[0][2]) for c in range(nc)]
+        cams = np.ascontiguousarray(np.stack([np.stack(
+            [synth.orbit_camera(r, scr[c][0], scr[c][1], start_deg=start[c]) for c in range(nc)])
+            for r in range(rounds)]), dtype=np.float32)          # (rounds, clouds, 4, 4)
+        saved = [d.clone() for d in devs]
+        torch.cuda.synchronize()
+        # served, saturated
+        srv = mm.mm_create_server(inst, 64 << 30, args.streams, args.max_batch, 3, 1,
+                                  args.tile, args.ppt, args.splits, args.grid, args.bin_threads)
+        for j, sp in enumerate(specs):
+            mm.mm_server_add_cloud(srv, mm.make_cloud_desc(allocs[j], sizes[j], 3, sp.seed, 0.001))
+        t0 = time.perf_counter()
+        ids = [mm.mm_server_submit(srv, c, c, cams[r, c], scr[c][0], scr[c][1])
+               for r in range(rounds) for c in range(nc)]
+        for i in ids:
+            mm.mm_server_wait(srv, i)
+        t_served = time.perf_counter() - t0
+        last_served = [mm.mm_server_read_frame(srv, c, scr[c][0], scr[c][1]) for c in range(nc)]
+        st = mm.mm_server_stats_get(srv)
+        mm.mm_destroy_server(srv)
+        # batched offline, from the same initial positions
+        for d, s0 in zip(devs, saved):
+            d.copy_(s0)
+        torch.cuda.synchronize()
+        clouds = [mm.make_cloud_desc(allocs[j], sizes[j], 3, sp.seed, 0.001, False)
+                  for j, sp in enumerate(specs)]
+        vds = [mm.make_batch_view_desc(c, scr[c][0], scr[c][1], cams[0, c]) for c in range(nc)]
+        b = mm.mm_create_batch(inst, 3, 1, clouds, vds)
+        Lb = mm.lib()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(rounds):
+            s = (Lb.mm_batch_set_cameras(b, 0, nc, mm._fptr(cams[r]))
+                 or Lb.mm_batch_step_render(b, r))
+            if s:
+                raise mm.MMError(s, "offline batch", mm.mm_last_error())
+        torch.cuda.synchronize()
+        t_batched = time.perf_counter() - t0
+        same = all(np.array_equal(mm.mm_batch_read_frame(b, c, scr[c][0], scr[c][1]), last_served[c])
+                   for c in range(nc))
+        mm.mm_destroy_batch(b)
+        for d, s0 in zip(devs, saved):
+            d.copy_(s0)
+        torch.cuda.synchronize()
+        n_req = rounds * nc
+        pts_round = float(sum(sizes))
+        return {"request_set": f"{rounds} rounds x {nc} clouds (session c: cloud c at "
+                               f"{'/'.join(f'{w}x{h}' for w, h in SERVED_SCREENS)} by c mod 3)",
+                "requests": n_req,
+                "served": {"frames_per_s": n_req / t_served,
+                           "Gpoints_per_s": pts_round * rounds / t_served / 1e9,
+                           "wall_s": t_served, "launches": st["launches"],
+                           "max_in_flight": st["max_in_flight"], "max_batch": st["max_batch"]},
+                "batched_offline": {"frames_per_s": n_req / t_batched,
+                                    "Gpoints_per_s": pts_round * rounds / t_batched / 1e9,
+                                    "wall_s": t_batched, "launches": rounds},
+                "served_over_batched": t_batched / t_served,
+                "last_frames_identical": bool(same)}
+
     count = args.requests
     print(f"bench served: 256 sessions, {len(specs)} clouds, {count} requests per run",
           file=sys.stderr, flush=True)
@@ -399,6 +468,9 @@ def bench_served(args) -> dict:
     for rate in (4 * args.rate, 16 * args.rate, float("inf")):
         runs.append(run(rate, count, 64 << 30, 3))
         print(f"  rate {rate}: {runs[-1]['frames_per_s']:.0f} frames/s", file=sys.stderr, flush=True)
+    vs = served_vs_batched(40)
+    print(f"  same request set: served {vs['served']['frames_per_s']:.0f} frames/s, batched offline "
+          f"{vs['batched_offline']['frames_per_s']:.0f} frames/s", file=sys.stderr, flush=True)
     for a in allocs:
         mm.mm_free(a)
     mm.mm_destroy_instance(inst)
@@ -416,6 +488,7 @@ def bench_served(args) -> dict:
         "p50_latency_ms": main_run["p50_latency_ms"],
         "p99_latency_ms": main_run["p99_latency_ms"],
         "runs": runs,
+        "served_vs_batched_offline": vs,
     }
 
 
