@@ -3,14 +3,15 @@
 Workload (default): 2^24 float3 points uniform in [0,1)^3 (seed 0), each
 frame displaces every point by a Philox draw of +-0.001 per coordinate, then
 splats it at 1920x1080 with a camera orbiting the cube centre (radius 2.5,
-fov 60 deg, 1 deg per frame), then resolves RGBA8. Eight frames per hipGraph
-launch, each with its own step and camera. Positions start resident in HBM;
-nothing crosses PCIe in the timed region.
+fov 60 deg, 1 deg per frame), then resolves RGBA8. One hipGraph launch per
+frame; the line also gives, beside it, the same frames at 8 per launch
+(mm_step_render_frames). Positions start resident in HBM; nothing crosses
+PCIe in the timed region.
 
 Prints ONE JSON line: throughput in Gpoints/s (value), frames/s, p50/p99
 frame time from the device clock stored by each timed frame's first kernel
 (and after the last), the roofline of the dominant kernel (the bin kernel,
-timed by events inside the frame graph on one frame in eight), the whole frame's
+timed by events inside the frame graph on one frame in 32), the whole frame's
 roofline, the host it ran on, and the CPU oracle timed on a bounded sample
 of the same workload.
 """
@@ -48,7 +49,13 @@ TRAFFIC = {
                    "digest": "94b7f6d8371b4f5e", "fetch_kib": 98395.0, "write_kib": 335980.7,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
-FRAMES_PER_LAUNCH = 8  # frames per graph launch (mm_step_render_frames)
+FRAMES_PER_LAUNCH = 1  # frames per graph launch: the workload is one hipGraph per frame
+MULTI_FRAMES = 8       # the extra measurement of several frames per launch
+# Frames per profiled frame: the profiled frame launches a second graph with
+# event-record nodes around the bin kernel, which costs that frame about
+# 35 us; one in 32 keeps that under 1.5 us per frame on average (measured:
+# 4.5 us per frame at one in 8) and still gives 31 samples in 1000 frames.
+PROFILE_EVERY = 32
 POINT_BYTES = 24   # float3 read + write per point and frame
 PIXEL_BYTES = 20   # key read + empty-key write (8 + 8) and RGBA8 write (4)
 
@@ -846,13 +853,14 @@ def main() -> int:
             np.stack([frame_camera(args.dist, first + k, w, h) for k in range(count)]),
             dtype=np.float32).reshape(-1)
 
-    def frames(cam_all, first, count, what):
-        # cam_all: count * 16 floats; the C entry point directly, so Python
+    def frames(cam_all, first, count, what, per=B):
+        # cam_all: count * 16 floats; the C entry points directly, so Python
         # adds as little as possible to the host side of a launch
-        for k0 in range(0, count, B):
-            c = min(B, count - k0)
+        for k0 in range(0, count, per):
+            c = min(per, count - k0)
             ptr = C.cast(cam_all.ctypes.data + 64 * k0, C.POINTER(C.c_float))
-            st = L.mm_step_render_frames(view, first + k0, c, ptr)
+            st = (L.mm_set_camera(view, ptr) or L.mm_step_render(view, first + k0)) if c == 1 \
+                else L.mm_step_render_frames(view, first + k0, c, ptr)
             if st:
                 raise mm.MMError(st, what, mm.mm_last_error())
 
@@ -868,10 +876,11 @@ def main() -> int:
         f += SETTLE_BLOCK
         torch.cuda.synchronize()
     F0, settle_frames = f, f - W
-    # HIP events inside the frame graph on the first frame of every launch
-    # (1 in B frames): the kernel durations of the roofline
-    mm.mm_profile_every(view, B)
-    prof_cap = (K + B - 1) // B
+    # HIP events inside the frame graph (on the first frame of a launch) on
+    # one frame in PROFILE_EVERY: the kernel durations of the roofline
+    every = max(B, PROFILE_EVERY // B * B)
+    mm.mm_profile_every(view, every)
+    prof_cap = (K + every - 1) // every
     # the cameras of the timed frames are inputs, like the points: converted
     # before the timed region
     cam_all = cameras(F0, K)
@@ -902,6 +911,21 @@ def main() -> int:
         mm.mm_mark_end(view)
         lat_spans = mm.mm_mark_read(view, R + 1)
         lat_source = f"a latency run of {R} frames after the {K} timed ones"
+    # beside the timed loop: the next frames at MULTI_FRAMES per graph launch
+    multi = None
+    if B == 1 and not args.overlap:
+        Fm = F0 + K + (LATENCY_FRAMES if K < MIN_P99_SAMPLES else 0)
+        M = max(MULTI_FRAMES, min(K, 1000) // MULTI_FRAMES * MULTI_FRAMES)
+        cam_m = cameras(Fm, M)
+        torch.cuda.synchronize()
+        tm0 = time.perf_counter()
+        frames(cam_m, Fm, M, "multi-frame loop", MULTI_FRAMES)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - tm0
+        multi = {"frames_per_launch": MULTI_FRAMES, "frames": M, "ms_per_step": tm / M * 1e3,
+                 "value": n * M / tm / 1e9, "unit": "Gpoints/s",
+                 "note": "the same frames, several per graph launch (mm_step_render_frames); "
+                         "not the one-graph-per-frame workload"}
     mm.mm_destroy_view(view)
     mm.mm_free(alloc)
     mm.mm_destroy_instance(inst)
@@ -942,7 +966,7 @@ def main() -> int:
         **latency_fields(lat_spans, lat_source, FRAME_MARKS),
         "timed_frames_p50_ms": float(np.percentile(frame_spans, 50)),
         "timed_frames_max_ms": float(np.max(frame_spans)),
-        "kernel_profiled_frames": f"{len(frame_ms)} (1 in {B} of the timed frames)",
+        "kernel_profiled_frames": f"{len(frame_ms)} (1 in {every} of the timed frames)",
         "graph_ms_profiled_mean": float(np.mean(frame_ms)),
         "point_kernel_ms": splat_avg,
         "rest_of_frame_ms": float(np.mean(resolve_ms)),
@@ -959,6 +983,9 @@ def main() -> int:
         "stream_copy_GBps": copy_ceiling,
         "host": host_info(),
     }
+    if multi:
+        multi["frame_roofline_frac"] = frame_bytes / (multi["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        out["multi_frame_launch"] = multi
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, w, h, args.cpu_frames, args.dist, args.footprint)
     print(json.dumps(out), flush=True)
