@@ -92,11 +92,7 @@ struct mm_view_s {
     // rest are the tile passes
     std::vector<mm::Launch> nodes;
     uint32_t frame_nodes = 1;
-    // two instantiations of the frame graph, launched in turn: updating the
-    // per-frame node of one does not touch the launch of the other, which may
-    // still be in flight
-    FrameGraph plain, plain2, timed;
-    uint32_t flip = 0;
+    FrameGraph plain, timed;
     MultiGraph multi;
     hipEvent_t spare[kFrameEvents] = {nullptr, nullptr, nullptr, nullptr};  // unprofiled multi frames
     std::vector<hipEvent_t> events;  // kFrameEvents per profiled frame
@@ -533,8 +529,7 @@ mm_status setup_splat(mm_view v) {
             v->nodes.push_back(mm::merge_launch(foot, static_cast<int>(shift), v->ntiles));
         if (foot == 3) v->nodes.push_back(mm::seam_launch(static_cast<int>(shift), v->ntiles));
     }
-    MM_TRY(build_graph(v, false, v->plain));
-    return build_graph(v, false, v->plain2);
+    return build_graph(v, false, v->plain);
 }
 
 void destroy_overlap(mm_view v);
@@ -542,7 +537,6 @@ void destroy_overlap(mm_view v);
 void teardown_splat(mm_view v) {
     if (v->rstream) (void)hipStreamSynchronize(v->rstream);
     destroy_graph(v->plain);
-    destroy_graph(v->plain2);
     destroy_graph(v->timed);
     destroy_multi(v->multi);
     v->profiling = false;
@@ -1170,7 +1164,7 @@ mm_status mm_step_render(mm_view v, uint32_t step) {
         first_arg = &pa;
     }
     void* args[] = {first_arg};
-    FrameGraph* fg = (v->flip ^= 1u) ? &v->plain2 : &v->plain;
+    FrameGraph* fg = &v->plain;
     if (v->profiling && v->prof_count < v->prof_cap && v->prof_skip++ % v->prof_every == 0) {
         const uint32_t k = v->prof_count++;
         for (int j = 0; j < kFrameEvents; ++j)
