@@ -19,7 +19,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmm.so")
+# MM_LIB names another build of the same library (e.g. one with host-side
+# sanitizers, for tests)
+LIB_PATH = os.environ.get("MM_LIB") or os.path.join(_HERE, "libmm.so")
 
 MM_OK = 0
 MM_ERR_INVALID_ARG = -1
