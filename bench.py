@@ -646,22 +646,19 @@ def bench_hostcopy(args) -> dict:
     from paper_2504_20937_amd import hostcopy
     import synth
 
-    import psutil
-
     n, w, h = 1 << args.log2n, args.width, args.height
     K = max(1, args.hostcopy_frames)
-    proc = psutil.Process()
 
     def dev_free() -> int:  # hipMemGetInfo
         torch.cuda.synchronize()
         return torch.cuda.mem_get_info(0)[0]
 
     pts = synth.uniform_cube(n, 0)
+    torch.zeros(1, device="cuda")            # the runtime's own set-up, before any delta
     f0 = dev_free()
     dev = torch.from_numpy(pts).cuda()
     dev_positions = f0 - dev_free()          # both paths keep the positions on the device
     del pts
-    rss0 = proc.memory_info().rss
     host = torch.empty((n, 3), dtype=torch.float32, pin_memory=True)
     frame = np.empty((h, w), dtype=np.uint32)
     frame.fill(0)
@@ -690,7 +687,6 @@ def bench_hostcopy(args) -> dict:
         t_copy += c - b
         t_render += d - c
     elapsed = time.perf_counter() - t0
-    host_rss = proc.memory_info().rss - rss0  # pinned copy, frame, the render's per-thread buffers
     # the device path on the same workload, for the ratio
     G = 200
     for f in range(20):
@@ -719,10 +715,11 @@ def bench_hostcopy(args) -> dict:
         "displace_ms": t_disp / K * 1e3, "copy_ms": t_copy / K * 1e3,
         "render_ms": t_render / K * 1e3,
         "pcie_GBps": 12.0 * n * K / t_copy / 1e9,
-        "memory": {"how": "device: hipMemGetInfo free bytes before and after each allocation; "
-                          "host: resident set growth over the host-copy frames",
+        "memory": {"how": "device: hipMemGetInfo free bytes before and after each allocation "
+                          "(after the runtime's own set-up); host: the sizes allocated (pinned "
+                          "positions, frame, the render's per-thread depth buffers)",
                    "hostcopy_device_bytes": dev_positions,
-                   "hostcopy_host_bytes": host_rss,
+                   "hostcopy_host_bytes": 12 * n + 4 * w * h + 8 * w * h * threads,
                    "device_path_bytes": dev_positions + dev_view,
                    "device_path_view_bytes": dev_view,
                    "device_path_over_hostcopy_device": (dev_positions + dev_view) / dev_positions},
