@@ -251,31 +251,34 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
     for (uint32_t base = w_lo; base < w_hi; base += kCol) {
         const uint32_t nb = min(kCol, w_hi - base);
         __syncthreads();  // keys initialised / previous pass done with the LDS
-        // Branch-free: lanes past the column's end read its last entry (count
-        // forced to 0), so all of a lane's table loads are in flight together.
+        // Branch-free within a lane: lanes past the column's end read its last
+        // entry (count forced to 0), so all of a lane's table loads are in
+        // flight together. Entries k >= per, which no lane holds for a column
+        // this short (a small cloud), are neither loaded nor counted.
+        const uint32_t per = (nb + NT - 1u) / NT;  // in 1 .. kPer, the same for the block
         uint32_t cs[kPer], cn[kPer];
         if (v.tcol) {  // tile-major copy: entries t and t + 1 of each row, contiguous
             const uint16_t* e0 = v.tcol + static_cast<uint64_t>(t) * v.tcol_stride + base;
             const uint16_t* e1 = e0 + v.tcol_stride;
 #pragma unroll
             for (uint32_t k = 0; k < kPer; ++k) {
-                const uint32_t c = min(tid * kPer + k, nb - 1u);
-                cs[k] = e0[c];
-                cn[k] = e1[c];
+                const uint32_t c = min(tid * per + k, nb - 1u);
+                cs[k] = k < per ? e0[c] : 0u;
+                cn[k] = k < per ? e1[c] : 0u;
             }
         } else {
 #pragma unroll
             for (uint32_t k = 0; k < kPer; ++k) {
-                const uint32_t c = tid * kPer + k;
+                const uint32_t c = tid * per + k;
                 const uint16_t* row = v.table + static_cast<uint64_t>(base + min(c, nb - 1u)) * stride;
-                cs[k] = row[t];
-                cn[k] = row[t + 1];
+                cs[k] = k < per ? row[t] : 0u;
+                cn[k] = k < per ? row[t + 1] : 0u;
             }
         }
         uint32_t tc = 0, tr = 0;  // this thread's records and non-empty runs
 #pragma unroll
         for (uint32_t k = 0; k < kPer; ++k) {
-            cn[k] = tid * kPer + k < nb ? cn[k] - cs[k] : 0u;
+            cn[k] = k < per && tid * per + k < nb ? cn[k] - cs[k] : 0u;
             tc += cn[k];
             tr += cn[k] != 0u;
         }
@@ -298,7 +301,7 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
 #pragma unroll
         for (uint32_t k = 0; k < kPer; ++k) {
             if (cn[k] != 0u) {
-                const uint32_t c = tid * kPer + k;
+                const uint32_t c = tid * per + k;
                 roff[orr] = oc;
                 // record f of this run is seg[base P + c P + start + f - oc]
                 runs[orr] = make_uint2(c * P + cs[k] - oc, (base + c) * P);
