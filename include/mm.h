@@ -489,7 +489,9 @@ typedef struct {
     uint32_t tile;              /* tile side of every view: 16, 32 or 64; 0 = auto */
     uint32_t points_per_thread; /* 4, 8 or 16; 0 = auto */
     uint32_t splits;            /* workgroups per tile: 1, 2, 4 or 8 for every view;
-                                   0 = per view by the size of its cloud */
+                                   0 = per view by its cloud's points per tile
+                                   (n / tiles: 2 from 4096 or from 256 bin
+                                   workgroups, 4 from 8192, 8 from 16384) */
     uint32_t grid_blocks;       /* 0: one workgroup per work item; else a persistent
                                    grid of that many workgroups per pass, each
                                    looping over work items */

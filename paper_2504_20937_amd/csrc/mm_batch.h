@@ -56,8 +56,10 @@ struct Node {
 };
 
 // Tiles, bin workgroups and splits of every view (splits 0: by cloud size).
+// Tiles, bin workgroups and splits of every view; auto splits (splits == 0)
+// never exceed max_splits, which the caller's partial-block buffers hold.
 void shape_views(std::vector<PlanView>& views, const std::vector<Cloud>& clouds, uint32_t side,
-                 uint32_t P, uint32_t splits);
+                 uint32_t P, uint32_t splits, uint32_t max_splits);
 // Work tables of a launch; views grouped by cloud, their scratch set. With
 // the 1x1 footprint, views of one split get no merge items (the tile pass
 // resolves them).

@@ -119,14 +119,23 @@ void xcd_tile_items(const std::vector<PlanView>& views, std::vector<uint2>& out)
 }
 
 void shape_views(std::vector<PlanView>& views, const std::vector<Cloud>& clouds, uint32_t side,
-                 uint32_t P, uint32_t splits) {
+                 uint32_t P, uint32_t splits, uint32_t max_splits) {
     for (PlanView& v : views) {
         const Cloud& c = clouds[v.cloud];
         v.tiles_x = (v.width + side - 1) / side;
         v.tiles_y = (v.height + side - 1) / side;
         v.ntiles = v.tiles_x * v.tiles_y;
         v.num_wg = static_cast<uint32_t>((c.n + P - 1) / P);
-        v.splits = splits != 0 ? splits : (v.num_wg >= 256 ? 2u : 1u);
+        // Auto: by the view's points per tile. A tile-pass item takes a
+        // share of one tile's records and the densest tile's item bounds the
+        // pass; a clustered cloud puts many times the mean on its densest
+        // tiles (in the 64-cloud set, 1.1 M records on one 32-pixel tile of a
+        // 256-pixel view of 2^22 points: 8 splits make that item 137 K).
+        const uint64_t per_tile = c.n / std::max<uint32_t>(1u, v.ntiles);
+        uint32_t s = v.num_wg >= 256 || per_tile >= 4096 ? 2u : 1u;
+        if (per_tile >= 8192) s = 4;
+        if (per_tile >= 16384) s = 8;
+        v.splits = splits != 0 ? splits : std::min(s, max_splits);
     }
 }
 
@@ -270,7 +279,7 @@ mm_status Plan::setup(mm_instance inst, const mm_batch_tuning& t) {
     hipError_t e = hipSuccess;
 
     // per-view shape and scratch
-    shape_views(views, clouds, side, P, t.splits);
+    shape_views(views, clouds, side, P, t.splits, 8u);  // partial blocks sized per view below
     total_tiles = 0;
     for (PlanView& v : views) total_tiles += v.ntiles;
     e = alloc_n(&active, static_cast<uint64_t>(total_tiles) + 1);

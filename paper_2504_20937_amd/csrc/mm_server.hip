@@ -191,7 +191,11 @@ mm_status mm_server_s::launch_slot(Slot& sl, const std::vector<Sched::Item>& ite
         v.active = buf.active;
         views.push_back(v);
     }
-    mmb::shape_views(views, cl, side, P, desc.tuning.splits);
+    // frame buffers hold splits_cap partial blocks per tile (fb_bytes)
+    mmb::shape_views(views, cl, side, P, desc.tuning.splits, splits_cap);
+    for (const mmb::PlanView& v : views)
+        if (v.splits > splits_cap)
+            return fail(MM_ERR_HIP, "server: %u splits for a frame buffer of %u", v.splits, splits_cap);
     MM_TRY(mmb::build_tables(cl, views, P, desc.footprint, sl.img));
     const size_t stat = sl.img.stat.size(), frame = sl.img.frame.size();
     const size_t total = stat + frame;
