@@ -169,3 +169,32 @@ def test_compute_sections_ping_pong(rig):
     torch.cuda.synchronize()
     for b, ref in zip(bufs, host):
         assert same_bits(rig.positions(b), ref)
+
+
+def test_overlap_frames_per_launch_and_marks(rig):
+    """With frame overlap, mm_step_render_frames enqueues its frames one by
+    one (the same frames, the buffer one frame behind until the flush), and
+    the frame marks, stored by each frame's bin kernel, cover every frame."""
+    say("case: overlap + mm_step_render_frames + marks, 3D uniform, 150001 points, 480x320")
+    mm = rig.mm
+    n, w, h, seed, amp = 150001, 480, 320, 21, 0.002
+    pts = synth.uniform_cube(n, seed=seed)
+    dev, alloc = rig.cloud(pts)
+    view = rig.view(alloc, n, 3, w, h, 1, seed, amp, False, synth.orbit_camera(0, w, h))
+    mm.mm_set_frame_overlap(view, True)
+    ref = pts.copy()
+    mm.mm_mark_begin(view, 12 + 1)
+    cams = [synth.orbit_camera(7 * f, w, h) for f in range(12)]
+    mm.mm_step_render_frames(view, 0, 5, cams[:5])
+    mm.mm_step_render_frames(view, 5, 7, cams[5:])
+    for f in range(12):
+        oracle.displace(ref, seed, f, amp, False)
+    mm.mm_mark_end(view)  # draws the pending frame first
+    iv = mm.mm_mark_read(view, 13)
+    assert iv.shape == (12,) and np.all(iv > 0), iv
+    want = oracle.render(ref, seed, cams[-1], w, h, 1)
+    got = mm.mm_read_frame(view, w, h)
+    assert np.array_equal(got, want), first_diff(got, want)
+    assert same_bits(rig.positions(dev), ref)
+    mm.mm_destroy_view(view)
+    mm.mm_free(alloc)
