@@ -131,8 +131,13 @@ template <int FOOT, int SHIFT, uint32_t NT = kTileThreads>
 struct TileShape {
     static constexpr uint32_t S = 1u << SHIFT;
     static constexpr uint32_t A = FOOT == 3 ? S + 2 : S;
-    static constexpr uint32_t kCol = 2048;     // bin workgroups per pass over the column
-    static constexpr uint32_t kSeg = 1u << 17;  // records per segment of a pass
+    // Batched tile workgroups (256 threads) take many small tiles: a shorter
+    // pass and segment leave 25 KB of LDS a workgroup instead of 49 KB, so
+    // five workgroups share a CU instead of three (the 64-cloud batch frame:
+    // 0.96 against 1.03 ms). Clouds of more bin workgroups take more passes.
+    static constexpr uint32_t kCol = NT == 256 ? 1024 : 2048;  // bin workgroups per pass over the column
+    static constexpr uint32_t kSeg = NT == 256 ? 1u << 15 : 1u << 17;  // records per segment of a pass
+    static constexpr uint32_t kWindows = NT == 256 ? 6 : 12;  // 64-record windows in flight per lane
     // LDS words beside the keys: run offsets (kCol + 1, padded to even), run
     // address bias and index base (2 kCol), the segment's run-start bitmap
     // (kSeg / 32) and the scan's wave sums (2 per wave)
@@ -325,9 +330,12 @@ __device__ __forceinline__ void tile_range(const TileView& v, uint32_t t, uint32
             const uint32_t nwin = (len + 63u) >> 6;
             const uint32_t r0 = s0 + (nwin * wave / kWaves) * 64u;
             const uint32_t r1 = s0 + min(len, (nwin * (wave + 1u) / kWaves) * 64u);
+            // windows in flight per lane: 12 for the few dense tiles of one view;
+            // 6 for the many small batched tiles, whose workgroups gain more from
+            // sharing a CU (72 VGPRs, six a CU: 0.92 against 0.96 ms per batch frame)
             if (r0 < r1)
-                splat_segment<S, 12>(seg, keys, roff, runs,
-                                     reinterpret_cast<const uint64_t*>(bits), nruns, s0, r0, r1);
+                splat_segment<S, Sh::kWindows>(seg, keys, roff, runs,
+                                               reinterpret_cast<const uint64_t*>(bits), nruns, s0, r0, r1);
         }
     }
     __syncthreads();
