@@ -602,11 +602,13 @@ def bench_edges(args) -> dict:
 
 
 def bench_cobound(args) -> dict:
-    """The ALU co-bound of the bin pass: `mm_cobound` (built beside the
+    """The co-bounds of the two passes: `mm_cobound` (built beside the
     library) times the per-point Philox draw, and the draw with the
     displacement and projection, in the bin kernel's launch shape without the
     position traffic, and the launch with only its index arithmetic and one
-    store per thread. Reported beside the bin kernel's time from a frame run."""
+    store per thread (the bin pass's ALU co-bound); and one tile workgroup
+    per CU streaming a tile's worth of 8-byte records with nothing else (the
+    tile pass's co-bound: what one CU reads of a dense tile per second)."""
     import subprocess
 
     from paper_2504_20937_amd import build as mmbuild
@@ -620,6 +622,21 @@ def bench_cobound(args) -> dict:
     probe = json.loads(r.stdout.strip().splitlines()[-1])
     n = probe["points"]
     alu_us = probe["displace_project_us"] - probe["index_store_us"]
+    # the tile pass's co-bound: one 1024-thread workgroup per CU streaming
+    # 8-byte words (the mean and the heaviest active tile's records at 2^24
+    # points and 1080p), durations from the device clock at each workgroup's
+    # start and end
+    st = probe["stream"]
+    mean_b, heavy_b = 8 * st["mean_words"], 8 * st["heavy_words"]
+    tile_stream = {
+        "mean_tile_bytes": mean_b,
+        "heavy_tile_bytes": heavy_b,
+        "every_cu_streaming_us": st["even_u12"]["wg_mean_us"],
+        "every_cu_streaming_GBps_per_cu": mean_b / st["even_u12"]["wg_mean_us"] / 1e3,
+        "heavy_workgroup_us": st["heavy_u12"]["wg0_us"],
+        "heavy_workgroup_GBps": heavy_b / st["heavy_u12"]["wg0_us"] / 1e3,
+        "heavy_workgroup_us_24_windows": st["heavy_u24"]["wg0_us"],
+    }
     return {
         "metric": "bin pass ALU co-bound: per-point displace + project time without memory traffic",
         "value": alu_us,
@@ -632,6 +649,7 @@ def bench_cobound(args) -> dict:
         "philox_us": probe["philox_us"] - probe["index_store_us"],
         "displace_project_us": alu_us,
         "launch_and_store_us": probe["index_store_us"],
+        "tile_stream": tile_stream,
         "probe": probe,
     }
 

@@ -1,18 +1,31 @@
-// Integer/FP32 ALU co-bound of the bin pass: the per-point arithmetic of a
-// frame (the Philox4x32-10 draw; the draw, the displacement and the
-// projection) timed without the position traffic. The launch has the shape of
-// the plain bin kernel at its default tuning (1024-thread workgroups, 8
-// points per thread); each thread folds its results into one 4-byte store so
-// the compiler keeps all of the work. A kernel with only the index arithmetic
-// and that store gives the launch and store overhead.
+// Co-bounds of the two passes of a binned frame, each timed without the rest
+// of the frame.
+//
+// Bin pass (integer/FP32 ALU): the per-point arithmetic of a frame (the
+// Philox4x32-10 draw; the draw, the displacement and the projection) without
+// the position traffic. The launch has the shape of the plain bin kernel at
+// its default tuning (1024-thread workgroups, 8 points per thread); each
+// thread folds its results into one 4-byte store so the compiler keeps all of
+// the work. A kernel with only the index arithmetic and that store gives the
+// launch and store overhead.
+//
+// Tile pass (one CU's record stream): a dense tile is taken by one 1024-thread
+// workgroup on one CU, which streams the tile's 8-byte records in 64-record
+// windows per wave. The stream probe runs one such workgroup per CU (dynamic
+// LDS keeps a second one off the CU), each reading its own contiguous range
+// of 8-byte words with U windows in flight per lane and no other work, and
+// stores the device clock at each workgroup's start and end. Workgroup 0 can
+// take a longer range (the heaviest tile) than the others (the mean tile).
 //
 //   mm_cobound [log2 points = 24] [launches = 50]
 //
 // prints one JSON line with the mean time per launch of each probe.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <vector>
 
 #include "mm_device.h"
 
@@ -62,6 +75,33 @@ __global__ __launch_bounds__(kThreads) void point_probe(uint32_t* out, CloudArgs
             acc ^= bits ^ (static_cast<uint32_t>(px) << 16) ^ static_cast<uint32_t>(py);
     }
     out[blockIdx.x * kThreads + threadIdx.x] = acc;
+}
+
+// Workgroup b reads words [b * stride, b * stride + n_b) of src, n_b = heavy
+// for b = 0 and mean otherwise (both at most stride); slot 2 b and 2 b + 1 of
+// clk get the device clock at its start and end.
+template <int U>
+__global__ __launch_bounds__(kThreads) void stream_probe(const uint64_t* src, uint32_t* out,
+                                                         uint64_t* clk, uint32_t stride,
+                                                         uint32_t mean, uint32_t heavy) {
+    extern __shared__ uint32_t hold[];  // sized by the launch only: one workgroup per CU
+    if (threadIdx.x == 0) clk[2 * blockIdx.x] = wall_clock64();
+    const uint32_t n = blockIdx.x == 0 ? heavy : mean;
+    const uint64_t* p = src + static_cast<uint64_t>(blockIdx.x) * stride;
+    uint64_t acc = 0;
+    for (uint32_t w = threadIdx.x; w < n; w += kThreads * U) {
+        uint64_t r[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = w + static_cast<uint32_t>(u) * kThreads;
+            r[u] = i < n ? p[i] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc ^= r[u];
+    }
+    out[blockIdx.x * kThreads + threadIdx.x] = static_cast<uint32_t>(acc ^ (acc >> 32));
+    __syncthreads();
+    if (threadIdx.x == 0) clk[2 * blockIdx.x + 1] = wall_clock64();
 }
 
 #define CHECK(call)                                                                      \
@@ -130,7 +170,63 @@ int main(int argc, char** argv) {
     std::printf("{\"points\": %u, \"threads\": %u, \"points_per_thread\": %d, \"launches\": %d",
                 c.n, kThreads, kPpt, launches);
     for (int k = 0; k < 3; ++k) std::printf(", \"%s\": %.2f", names[k], us[k]);
-    std::printf(", \"check\": %u}\n", probe);
+    std::printf(", \"check\": %u", probe);
+
+    // The tile pass's record stream: one workgroup per CU. The mean and
+    // heaviest ranges are those of the 1x1 tile pass at 2^24 points and
+    // 1920x1080 (about 65,000 and 150,000 records per active tile).
+    int dev = 0, cus = 0, khz = 0;
+    CHECK(hipGetDevice(&dev));
+    CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const uint32_t mean = 65536, heavy = 150000, stride = 150016;
+    uint64_t* src = nullptr;
+    uint64_t* clk = nullptr;
+    uint32_t* sout = nullptr;
+    CHECK(hipMalloc(&src, sizeof(uint64_t) * stride * static_cast<size_t>(cus)));
+    CHECK(hipMalloc(&clk, sizeof(uint64_t) * 2 * static_cast<size_t>(cus)));
+    CHECK(hipMalloc(&sout, sizeof(uint32_t) * kThreads * static_cast<size_t>(cus)));
+    CHECK(hipMemset(src, 0x5a, sizeof(uint64_t) * stride * static_cast<size_t>(cus)));
+    int lds_max = 0;
+    CHECK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // of 160 KB of LDS per CU, 96 KB leave no room for a second workgroup
+    const size_t hold = std::min<size_t>(96 * 1024, static_cast<size_t>(lds_max));
+    std::vector<uint64_t> t(2 * static_cast<size_t>(cus));
+    std::printf(", \"stream\": {\"cus\": %d, \"lds_hold\": %zu, \"mean_words\": %u, \"heavy_words\": %u",
+                cus, hold, mean, heavy);
+    for (int which = 0; which < 4; ++which) {
+        const uint32_t hv = which & 1 ? heavy : mean;
+        const int U = which < 2 ? 12 : 24;
+        float ms = 0.0f;
+        double first = 0.0, rest = 0.0;
+        for (int pass = 0; pass < 2; ++pass) {
+            CHECK(hipEventRecord(e0, nullptr));
+            for (int it = 0; it < launches; ++it) {
+                if (U == 12)
+                    hipLaunchKernelGGL(stream_probe<12>, dim3(cus), dim3(kThreads), hold, nullptr, src,
+                                       sout, clk, stride, mean, hv);
+                else
+                    hipLaunchKernelGGL(stream_probe<24>, dim3(cus), dim3(kThreads), hold, nullptr, src,
+                                       sout, clk, stride, mean, hv);
+            }
+            CHECK(hipGetLastError());
+            CHECK(hipEventRecord(e1, nullptr));
+            CHECK(hipEventSynchronize(e1));
+            CHECK(hipEventElapsedTime(&ms, e0, e1));
+        }
+        // workgroup durations of the last launch, in microseconds
+        CHECK(hipMemcpy(t.data(), clk, sizeof(uint64_t) * t.size(), hipMemcpyDeviceToHost));
+        first = static_cast<double>(t[1] - t[0]) * 1000.0 / khz;
+        for (int b = 1; b < cus; ++b) rest += static_cast<double>(t[2 * b + 1] - t[2 * b]) * 1000.0 / khz;
+        rest /= cus - 1;
+        std::printf(", \"%s_u%d\": {\"launch_us\": %.2f, \"wg0_us\": %.2f, \"wg_mean_us\": %.2f}",
+                    which & 1 ? "heavy" : "even", U, 1000.0f * ms / static_cast<float>(launches), first,
+                    rest);
+    }
+    std::printf("}}\n");
+    CHECK(hipFree(src));
+    CHECK(hipFree(clk));
+    CHECK(hipFree(sout));
     CHECK(hipFree(out));
     return 0;
 }
