@@ -638,7 +638,7 @@ def bench_cobound(args) -> dict:
         "heavy_workgroup_us_24_windows": st["heavy_u24"]["wg0_us"],
     }
     return {
-        "metric": "bin pass ALU co-bound: per-point displace + project time without memory traffic",
+        "metric": "bin pass ALU co-bound: per-point displace + project time without memory traffic (with the pass's memory co-bound and one CU's record stream beside it)",
         "value": alu_us,
         "unit": "us per launch",
         "n_gpus": 1,
@@ -649,6 +649,10 @@ def bench_cobound(args) -> dict:
         "philox_us": probe["philox_us"] - probe["index_store_us"],
         "displace_project_us": alu_us,
         "launch_and_store_us": probe["index_store_us"],
+        # the bin pass's bytes alone (12 B read + 12 B written in place + an
+        # 8 B record per point), the memory co-bound of the bin kernel
+        "bin_traffic_us": probe["traffic_us"],
+        "bin_traffic_TBps": probe["traffic_bytes"] / probe["traffic_us"] / 1e6,
         "tile_stream": tile_stream,
         "probe": probe,
     }

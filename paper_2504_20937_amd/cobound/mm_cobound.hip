@@ -9,6 +9,12 @@
 // the work. A kernel with only the index arithmetic and that store gives the
 // launch and store overhead.
 //
+// Bin pass (memory): the same launch moving only the bin kernel's bytes per
+// point, with its access kinds: the position read and written in place
+// (12-byte non-temporal accesses) and an 8-byte record write, coalesced,
+// with no arithmetic and no sort; what the HBM traffic of the pass costs by
+// itself (the table row, 1.5% of the bytes at 1080p, is left out).
+//
 // Tile pass (one CU's record stream): a dense tile is taken by one 1024-thread
 // workgroup on one CU, which streams the tile's 8-byte records in 64-record
 // windows per wave. The stream probe runs one such workgroup per CU (dynamic
@@ -75,6 +81,19 @@ __global__ __launch_bounds__(kThreads) void point_probe(uint32_t* out, CloudArgs
             acc ^= bits ^ (static_cast<uint32_t>(px) << 16) ^ static_cast<uint32_t>(py);
     }
     out[blockIdx.x * kThreads + threadIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void traffic_probe(float* pos, uint64_t* rec) {
+    const uint32_t base = blockIdx.x * (kThreads * kPpt);
+    float x[kPpt], y[kPpt], z[kPpt];
+#pragma unroll
+    for (int k = 0; k < kPpt; ++k) load_point<3>(pos, base + k * kThreads + threadIdx.x, x[k], y[k], z[k]);
+#pragma unroll
+    for (int k = 0; k < kPpt; ++k) {
+        const uint32_t i = base + k * kThreads + threadIdx.x;
+        store_point<3>(pos, i, x[k], y[k], z[k]);
+        rec[i] = (static_cast<uint64_t>(__float_as_uint(z[k])) << 32) | i;
+    }
 }
 
 // Workgroup b reads words [b * stride, b * stride + n_b) of src, n_b = heavy
@@ -165,12 +184,34 @@ int main(int argc, char** argv) {
             us[which] = 1000.0f * ms / static_cast<float>(launches);
         }
     }
+    // the bin pass's bytes alone: positions in place and one record per point
+    float* pos = nullptr;
+    uint64_t* rec = nullptr;
+    CHECK(hipMalloc(&pos, 12ull * c.n));
+    CHECK(hipMalloc(&rec, 8ull * c.n));
+    CHECK(hipMemset(pos, 0, 12ull * c.n));
+    float traffic_us = 0.0f;
+    for (int pass = 0; pass < 2; ++pass) {
+        CHECK(hipEventRecord(e0, nullptr));
+        for (int it = 0; it < launches; ++it)
+            hipLaunchKernelGGL(traffic_probe, dim3(blocks), dim3(kThreads), 0, nullptr, pos, rec);
+        CHECK(hipGetLastError());
+        CHECK(hipEventRecord(e1, nullptr));
+        CHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        traffic_us = 1000.0f * ms / static_cast<float>(launches);
+    }
+    CHECK(hipFree(pos));
+    CHECK(hipFree(rec));
+
     uint32_t probe = 0;
     CHECK(hipMemcpy(&probe, out, sizeof probe, hipMemcpyDeviceToHost));
     std::printf("{\"points\": %u, \"threads\": %u, \"points_per_thread\": %d, \"launches\": %d",
                 c.n, kThreads, kPpt, launches);
     for (int k = 0; k < 3; ++k) std::printf(", \"%s\": %.2f", names[k], us[k]);
-    std::printf(", \"check\": %u", probe);
+    std::printf(", \"check\": %u, \"traffic_us\": %.2f, \"traffic_bytes\": %llu", probe, traffic_us,
+                32ull * c.n);
 
     // The tile pass's record stream: one workgroup per CU. The mean and
     // heaviest ranges are those of the 1x1 tile pass at 2^24 points and
