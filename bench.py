@@ -636,6 +636,11 @@ def bench_cobound(args) -> dict:
         "heavy_workgroup_us": st["heavy_u12"]["wg0_us"],
         "heavy_workgroup_GBps": heavy_b / st["heavy_u12"]["wg0_us"] / 1e3,
         "heavy_workgroup_us_24_windows": st["heavy_u24"]["wg0_us"],
+        # every CU reading the heaviest tile's words: contiguously, and in the
+        # tile pass's layout (runs of 73 at misaligned or 1 KB-aligned offsets)
+        "every_cu_heavy_contiguous_us": st["contiguous_wg_us"],
+        "every_cu_heavy_runs_us": st["runs_wg_us"],
+        "every_cu_heavy_aligned_runs_us": st["aligned_runs_wg_us"],
     }
     return {
         "metric": "bin pass ALU co-bound: per-point displace + project time without memory traffic (with the pass's memory co-bound and one CU's record stream beside it)",

@@ -22,6 +22,8 @@
 // of 8-byte words with U windows in flight per lane and no other work, and
 // stores the device clock at each workgroup's start and end. Workgroup 0 can
 // take a longer range (the heaviest tile) than the others (the mean tile).
+// Last, every workgroup reads the heaviest tile's words contiguously, and as
+// the tile pass meets them: short runs at scattered, misaligned offsets.
 //
 //   mm_cobound [log2 points = 24] [launches = 50]
 //
@@ -96,10 +98,20 @@ __global__ __launch_bounds__(kThreads) void traffic_probe(float* pos, uint64_t* 
     }
 }
 
-// Workgroup b reads words [b * stride, b * stride + n_b) of src, n_b = heavy
-// for b = 0 and mean otherwise (both at most stride); slot 2 b and 2 b + 1 of
-// clk get the device clock at its start and end.
-template <int U>
+// The tile pass reads a tile's records as one run per bin workgroup: at
+// 2^24 points and 1080p the heaviest tile's 150,000 records come in runs of
+// about 73 (150,000 over 2,048 bin workgroups), each starting anywhere in
+// its cache line. LAYOUT 1 reads word f of a workgroup's stream as word
+// f mod kRunLen of run f / kRunLen, the runs kRunGap words apart at
+// misaligned offsets; LAYOUT 2 the same with every run starting on a 1 KB
+// boundary; LAYOUT 0 reads the words contiguously.
+constexpr uint32_t kRunLen = 73, kRunGap = 128;
+
+// Workgroup b reads n_b words of src from word b * stride on (n_b = heavy
+// for b = 0 and mean otherwise; the layout keeps every word below
+// (b + 1) * stride); slot 2 b and 2 b + 1 of clk get the device clock at its
+// start and end.
+template <int U, int LAYOUT>
 __global__ __launch_bounds__(kThreads) void stream_probe(const uint64_t* src, uint32_t* out,
                                                          uint64_t* clk, uint32_t stride,
                                                          uint32_t mean, uint32_t heavy) {
@@ -113,7 +125,13 @@ __global__ __launch_bounds__(kThreads) void stream_probe(const uint64_t* src, ui
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t i = w + static_cast<uint32_t>(u) * kThreads;
-            r[u] = i < n ? p[i] : 0ull;
+            uint32_t a = i;
+            if constexpr (LAYOUT != 0) {
+                const uint32_t run = i / kRunLen, pos = i - run * kRunLen;
+                const uint32_t off = LAYOUT == 1 ? (run * 37u) % (kRunGap - kRunLen) : 0u;
+                a = run * kRunGap + off + pos;
+            }
+            r[u] = i < n ? p[a] : 0ull;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) acc ^= r[u];
@@ -220,7 +238,9 @@ int main(int argc, char** argv) {
     CHECK(hipGetDevice(&dev));
     CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     CHECK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-    const uint32_t mean = 65536, heavy = 150000, stride = 150016;
+    const uint32_t mean = 65536, heavy = 150000;
+    // room for the heaviest stream in runs: every word read stays below the next workgroup's
+    const uint32_t stride = (heavy + kRunLen - 1) / kRunLen * kRunGap;
     uint64_t* src = nullptr;
     uint64_t* clk = nullptr;
     uint32_t* sout = nullptr;
@@ -244,10 +264,10 @@ int main(int argc, char** argv) {
             CHECK(hipEventRecord(e0, nullptr));
             for (int it = 0; it < launches; ++it) {
                 if (U == 12)
-                    hipLaunchKernelGGL(stream_probe<12>, dim3(cus), dim3(kThreads), hold, nullptr, src,
+                    hipLaunchKernelGGL((stream_probe<12, 0>), dim3(cus), dim3(kThreads), hold, nullptr, src,
                                        sout, clk, stride, mean, hv);
                 else
-                    hipLaunchKernelGGL(stream_probe<24>, dim3(cus), dim3(kThreads), hold, nullptr, src,
+                    hipLaunchKernelGGL((stream_probe<24, 0>), dim3(cus), dim3(kThreads), hold, nullptr, src,
                                        sout, clk, stride, mean, hv);
             }
             CHECK(hipGetLastError());
@@ -263,6 +283,30 @@ int main(int argc, char** argv) {
         std::printf(", \"%s_u%d\": {\"launch_us\": %.2f, \"wg0_us\": %.2f, \"wg_mean_us\": %.2f}",
                     which & 1 ? "heavy" : "even", U, 1000.0f * ms / static_cast<float>(launches), first,
                     rest);
+    }
+    // every workgroup the heaviest tile's words, contiguous or in runs
+    const char* layouts[3] = {"contiguous", "runs", "aligned_runs"};
+    std::printf(", \"layout_words\": %u", heavy);
+    for (int layout = 0; layout < 3; ++layout) {
+        double mean_us = 0.0;
+        for (int it = 0; it < launches; ++it) {
+            if (layout == 0)
+                hipLaunchKernelGGL((stream_probe<12, 0>), dim3(cus), dim3(kThreads), hold, nullptr, src, sout,
+                                   clk, stride, heavy, heavy);
+            else if (layout == 1)
+                hipLaunchKernelGGL((stream_probe<12, 1>), dim3(cus), dim3(kThreads), hold, nullptr, src, sout,
+                                   clk, stride, heavy, heavy);
+            else
+                hipLaunchKernelGGL((stream_probe<12, 2>), dim3(cus), dim3(kThreads), hold, nullptr, src, sout,
+                                   clk, stride, heavy, heavy);
+            CHECK(hipGetLastError());
+            CHECK(hipMemcpy(t.data(), clk, sizeof(uint64_t) * t.size(), hipMemcpyDeviceToHost));
+            double m = 0.0;
+            for (int b = 0; b < cus; ++b) m += static_cast<double>(t[2 * b + 1] - t[2 * b]) * 1000.0 / khz;
+            if (it > 0 || launches == 1) mean_us += m / cus;  // the first launch warms up
+        }
+        mean_us /= launches > 1 ? launches - 1 : 1;
+        std::printf(", \"%s_wg_us\": %.2f", layouts[layout], mean_us);
     }
     std::printf("}}\n");
     CHECK(hipFree(src));
