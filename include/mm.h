@@ -530,6 +530,13 @@ mm_status mm_batch_profile_end(mm_batch batch, float* frame_ms, uint32_t* count)
  * renders it. Its frame therefore equals the plain frame of that cloud
  * after steps 0..k, whatever else is queued or in flight.
  *
+ * Streams: up to two launches are in flight on each stream. A cloud's (or
+ * a session's) requests in flight are all on one stream, and its next
+ * request goes into the next launch on that stream, behind the previous one
+ * in stream order, so saturated clouds share every launch while the next
+ * one is prepared on the host. Requests with nothing in flight go to a
+ * stream that is idle, so independent requests run side by side.
+ *
  * A session's frame buffer is its RGBA8 frame (4 B per pixel) plus the
  * per-tile scratch of the depth test; its screen is fixed by its first
  * request. It is held from admission until the session is closed, or until
@@ -546,7 +553,7 @@ mm_status mm_batch_profile_end(mm_batch batch, float* frame_ms, uint32_t* count)
  * The server's calls may come from any thread. */
 typedef struct {
     uint64_t fb_budget_bytes;   /* frame-buffer bytes the admitted sessions may hold */
-    uint32_t streams;           /* launches in flight at once: 1..4 */
+    uint32_t streams;           /* streams the launches run on: 1..4 (two launches each) */
     uint32_t max_batch;         /* requests per launch: 1..4096 */
     mm_domain domain;           /* of every cloud */
     uint32_t footprint;         /* 1 or 3 */

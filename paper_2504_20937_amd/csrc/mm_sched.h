@@ -6,9 +6,18 @@
 // calls HIP, so the policy also builds and runs on the host alone.
 //
 // Order and results: requests on one cloud run in submission order, the
-// k-th on a cloud with displacement step k, and at most one request per
-// cloud and per session is in flight at once (a cloud's next step must see
-// the previous one's positions; a session owns one frame buffer).
+// k-th on a cloud with displacement step k. A launch holds at most one
+// request per cloud and per session. Slots come in groups that share a
+// stream; a cloud's or a session's requests are in flight on one stream at a
+// time, so several of them can be (a cloud's next step runs after the
+// previous one's positions are written, in stream order; a session's frame
+// buffer is written by one launch after another).
+//
+// Chaining: a slot on the stream where a cloud is in flight takes that
+// cloud's next request, so saturated clouds go out together in every launch,
+// one launch queued behind the other, and the next launch is prepared on the
+// host while the previous one runs. A launch with no cloud to chain goes to
+// a stream with nothing in flight, so independent requests run side by side.
 //
 // Progress: when no launch is in flight and a request is pending, the next
 // schedule() launches one. The earliest pending request leads its cloud's
@@ -61,7 +70,9 @@ public:
         uint32_t width = 0, height = 0;
         bool has_screen = false;
         bool admitted = false;
-        bool busy = false;      // a request in flight
+        uint32_t inflight = 0;  // requests in flight (all on stream `stream`)
+        uint32_t stream = 0;
+        uint64_t mark = 0;      // the launch being packed that holds one of its requests
         bool closing = false;
         uint32_t queued = 0;    // requests submitted, not launched
         uint64_t last_use = 0;  // launch counter when last launched (LRU)
@@ -70,8 +81,10 @@ public:
 
     struct Cloud {
         uint32_t next_step = 0;
-        bool busy = false;
-        std::deque<uint64_t> queue;  // request ids in submission order
+        uint32_t inflight = 0;  // requests in flight (all on stream `stream`)
+        uint32_t stream = 0;
+        uint64_t mark = 0;      // the launch being packed that holds one of its requests
+        std::deque<uint64_t> queue;  // request ids not launched, in submission order
     };
 
     // One request of a launch, with the session that renders it.
@@ -93,8 +106,9 @@ public:
         virtual int query(uint32_t slot) = 0;
     };
 
-    Scheduler(Backend& be, uint64_t budget, uint32_t slots, uint32_t max_batch)
-        : be_(be), budget_(budget), max_batch_(max_batch), slots_(slots) {}
+    // slots / per_stream streams; slot k runs on stream k / per_stream.
+    Scheduler(Backend& be, uint64_t budget, uint32_t slots, uint32_t max_batch, uint32_t per_stream = 1)
+        : be_(be), budget_(budget), max_batch_(max_batch), per_stream_(per_stream), slots_(slots) {}
 
     Scheduler(const Scheduler&) = delete;
     Scheduler& operator=(const Scheduler&) = delete;
@@ -154,9 +168,9 @@ public:
                 r.t_done = now;
                 (q > 0 ? stats_.completed : stats_.dropped)++;
                 Session& s = sessions_[r.session];
-                s.busy = false;
-                clouds_[r.cloud].busy = false;
-                if (s.closing && s.queued == 0) close_now(s);
+                s.inflight--;
+                clouds_[r.cloud].inflight--;
+                if (s.closing && s.queued == 0 && s.inflight == 0) close_now(s);
             }
             sl.reqs.clear();
             sl.busy = false;
@@ -171,16 +185,18 @@ public:
     // launch was attempted (sent, or failed and its requests dropped).
     bool schedule() {
         if (failed_ || pending_.empty()) return false;
-        uint32_t slot = 0;
-        while (slot < slots_.size() && slots_[slot].busy) ++slot;
-        if (slot == slots_.size()) return false;
+        const int picked = pick_slot();
+        if (picked < 0) return false;
+        const uint32_t slot = static_cast<uint32_t>(picked), st = slot / per_stream_;
+        const uint64_t tag = ++tag_;
         std::vector<uint64_t> batch;
         bool no_memory = false;
         for (uint64_t id : pending_) {
             Request& r = requests_[id];
             Cloud& c = clouds_[r.cloud];
             Session& s = sessions_[r.session];
-            if (c.busy || c.queue.front() != id || s.busy) continue;
+            if (c.queue.front() != id || c.mark == tag || s.mark == tag) continue;
+            if ((c.inflight != 0 && c.stream != st) || (s.inflight != 0 && s.stream != st)) continue;
             if (!s.admitted) {
                 const int a = admit(s);
                 if (a < 0) {
@@ -189,8 +205,12 @@ public:
                 }
                 if (a == 0) continue;
             }
-            c.busy = true;
-            s.busy = true;
+            c.mark = tag;
+            s.mark = tag;
+            c.inflight++;
+            c.stream = st;
+            s.inflight++;
+            s.stream = st;
             batch.push_back(id);
             if (batch.size() >= max_batch_) break;
         }
@@ -199,8 +219,8 @@ public:
             // every other buffer given up: the server stops as after a failed
             // launch (a request left out would break its cloud's step order)
             for (uint64_t id : batch) {
-                sessions_[requests_[id].session].busy = false;
-                clouds_[requests_[id].cloud].busy = false;
+                sessions_[requests_[id].session].inflight--;
+                clouds_[requests_[id].cloud].inflight--;
             }
             drop_queued();
             return true;
@@ -233,8 +253,8 @@ public:
                 r.state = kDropped;
                 r.t_done = now;
                 stats_.dropped++;
-                sessions_[r.session].busy = false;
-                clouds_[r.cloud].busy = false;
+                sessions_[r.session].inflight--;
+                clouds_[r.cloud].inflight--;
             }
             sl.reqs.clear();
             sl.busy = false;
@@ -250,7 +270,7 @@ public:
         auto it = sessions_.find(session);
         if (it == sessions_.end()) return false;
         Session& s = it->second;
-        if (!s.busy && s.queued == 0) close_now(s);
+        if (s.inflight == 0 && s.queued == 0) close_now(s);
         else s.closing = true;
         return true;
     }
@@ -302,6 +322,39 @@ public:
     }
 
 private:
+    int free_slot_on(uint32_t stream) const {
+        for (uint32_t k = stream * per_stream_; k < (stream + 1) * per_stream_ && k < slots_.size(); ++k)
+            if (!slots_[k].busy) return static_cast<int>(k);
+        return -1;
+    }
+
+    // The slot of the next launch: a free slot on the stream of a cloud in
+    // flight whose next request is pending (that request and the cloud's
+    // later steps chain behind it), else a free slot on a stream with nothing
+    // in flight, else any free slot; -1 when none is free.
+    int pick_slot() {
+        for (uint64_t id : pending_) {
+            const Request& r = requests_[id];
+            const Cloud& c = clouds_[r.cloud];
+            if (c.inflight == 0 || c.queue.front() != id) continue;
+            const Session& s = sessions_[r.session];
+            if (s.inflight != 0 && s.stream != c.stream) continue;
+            const int k = free_slot_on(c.stream);
+            if (k >= 0) return k;
+        }
+        int any = -1;
+        for (uint32_t k = 0; k < slots_.size(); ++k) {
+            if (slots_[k].busy) continue;
+            bool idle = true;
+            const uint32_t st = k / per_stream_;
+            for (uint32_t j = st * per_stream_; j < (st + 1) * per_stream_ && j < slots_.size(); ++j)
+                idle = idle && !slots_[j].busy;
+            if (idle) return static_cast<int>(k);
+            if (any < 0) any = static_cast<int>(k);
+        }
+        return any;
+    }
+
     struct SlotState {
         bool busy = false;
         std::vector<uint64_t> reqs;
@@ -354,7 +407,7 @@ private:
         Session* victim = nullptr;
         for (auto& kv : sessions_) {
             Session& v = kv.second;
-            if (!v.admitted || v.busy || &v == &s) continue;
+            if (!v.admitted || v.inflight != 0 || &v == &s) continue;
             if (!victim) {
                 victim = &v;
                 continue;
@@ -388,7 +441,7 @@ private:
         stats_.dropped++;
         Session& s = sessions_[r.session];
         s.queued--;
-        if (s.closing && s.queued == 0 && !s.busy) close_now(s);
+        if (s.closing && s.queued == 0 && s.inflight == 0) close_now(s);
     }
 
     // After a failed launch nothing more is scheduled: every queued request
@@ -407,6 +460,7 @@ private:
     Backend& be_;
     uint64_t budget_;
     uint32_t max_batch_;
+    uint32_t per_stream_;
     std::vector<SlotState> slots_;
     std::vector<Cloud> clouds_;
     std::unordered_map<uint32_t, Session> sessions_;
@@ -416,6 +470,7 @@ private:
     uint64_t held_ = 0;                  // bytes of admitted and kept buffers
     uint64_t next_id_ = 1;
     uint32_t in_flight_ = 0;
+    uint64_t tag_ = 0;  // launches packed so far (marks)
     bool failed_ = false;
     mm_server_stats stats_{};
 };

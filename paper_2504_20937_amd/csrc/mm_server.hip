@@ -77,10 +77,15 @@ struct mm_server_s : Sched::Backend {
     std::thread worker;
     bool stop = false;
     std::vector<SCloud> clouds;
-    std::vector<Slot> slots;
+    std::vector<hipStream_t> streams;
+    std::vector<Slot> slots;  // kSlotsPerStream per stream, slot k on stream k / kSlotsPerStream
     Sched* sched = nullptr;
     uint32_t stamp = 0;
     uint32_t* stamps = nullptr;     // one device word per slot
+    // Two launches can be queued on a stream: the next one is packed and
+    // staged on the host while the previous one runs, and takes the clouds
+    // in flight there (stream order runs their steps one after the other).
+    static constexpr uint32_t kSlotsPerStream = 2;
 
     uint64_t fb_bytes(uint32_t w, uint32_t h) const override;
     bool alloc_buf(uint32_t w, uint32_t h, FrameBuf& out) override;
@@ -310,30 +315,35 @@ mm_status mm_create_server(mm_instance inst, const mm_server_desc* desc, mm_serv
     srv->P = threads * ppt;
     srv->splits_cap = t.splits ? t.splits : 2u;
     srv->desc.tuning = mm_batch_tuning{side, ppt, t.splits, t.grid_blocks, threads};
-    hipError_t e = dev_malloc(reinterpret_cast<void**>(&srv->stamps), 256 * desc->streams);
-    if (e == hipSuccess) e = hipMemset(srv->stamps, 0, 256 * desc->streams);
-    srv->slots.resize(desc->streams);
-    for (uint32_t k = 0; k < desc->streams && e == hipSuccess; ++k) {
+    const uint32_t nslots = desc->streams * mm_server_s::kSlotsPerStream;
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(&srv->stamps), 256 * nslots);
+    if (e == hipSuccess) e = hipMemset(srv->stamps, 0, 256 * nslots);
+    srv->streams.assign(desc->streams, nullptr);
+    for (uint32_t k = 0; k < desc->streams && e == hipSuccess; ++k)
+        e = hipStreamCreateWithFlags(&srv->streams[k], hipStreamNonBlocking);
+    srv->slots.resize(nslots);
+    for (uint32_t k = 0; k < nslots && e == hipSuccess; ++k) {
         Slot& sl = srv->slots[k];
-        e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        sl.stream = srv->streams[k / mm_server_s::kSlotsPerStream];
+        e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         sl.stamp_slot = srv->stamps + 64 * k;
     }
-    if (e != hipSuccess) {
-        for (Slot& sl : srv->slots) {
+    auto destroy_streams = [srv] {
+        for (Slot& sl : srv->slots)
             if (sl.done) (void)hipEventDestroy(sl.done);
-            if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        }
+        for (hipStream_t st : srv->streams)
+            if (st) (void)hipStreamDestroy(st);
+    };
+    if (e != hipSuccess) {
+        destroy_streams();
         if (srv->stamps) (void)hipFree(srv->stamps);
         delete srv;
         return hip_fail(e, "create_server: streams");
     }
-    srv->sched = new (std::nothrow) Sched(*srv, desc->fb_budget_bytes, desc->streams, desc->max_batch);
+    srv->sched = new (std::nothrow)
+        Sched(*srv, desc->fb_budget_bytes, nslots, desc->max_batch, mm_server_s::kSlotsPerStream);
     if (!srv->sched) {
-        for (Slot& sl : srv->slots) {
-            (void)hipEventDestroy(sl.done);
-            (void)hipStreamDestroy(sl.stream);
-        }
+        destroy_streams();
         (void)hipFree(srv->stamps);
         delete srv;
         return fail(MM_ERR_OUT_OF_MEMORY, "create_server: host allocation");
@@ -357,13 +367,13 @@ mm_status mm_destroy_server(mm_server srv) {
     srv->worker.join();
     srv->done_cv.notify_all();
     DeviceGuard guard(inst->device);
+    for (hipStream_t st : srv->streams) (void)hipStreamSynchronize(st);
     for (Slot& sl : srv->slots) {
-        (void)hipStreamSynchronize(sl.stream);
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.pinned) (void)hipHostFree(sl.pinned);
         (void)hipEventDestroy(sl.done);
-        (void)hipStreamDestroy(sl.stream);
     }
+    for (hipStream_t st : srv->streams) (void)hipStreamDestroy(st);
     srv->sched->free_all();
     delete srv->sched;
     for (SCloud& c : srv->clouds) {
@@ -488,7 +498,7 @@ mm_status mm_server_read_frame(mm_server srv, uint32_t session, void* host_rgba,
     std::unique_lock<std::mutex> lk(srv->mu);
     Sched::Session* s = srv->sched->session(session);
     if (!s) return fail(MM_ERR_INVALID_ARG, "server_read_frame: unknown session %u", session);
-    srv->done_cv.wait(lk, [&] { return !s->busy || srv->stop; });
+    srv->done_cv.wait(lk, [&] { return s->inflight == 0 || srv->stop; });
     if (!s->admitted) return fail(MM_ERR_NOT_READY, "server_read_frame: session %u holds no frame buffer", session);
     const size_t need = static_cast<size_t>(s->width) * s->height * 4;
     if (bytes < need) return fail(MM_ERR_INVALID_ARG, "server_read_frame: %zu bytes < %zu", bytes, need);

@@ -3,6 +3,7 @@
 // and run by tests/test_sched_cpu.py, under AddressSanitizer and
 // UndefinedBehaviorSanitizer. Prints "ok <case>" per case and "all ok" at
 // the end; any failed check prints its line and exits with status 1.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -45,8 +46,10 @@ struct Fake : Sched::Backend {
     std::vector<int> slot_launch;   // per slot: launch index
     std::vector<Launched> log;
     std::set<int> live;             // ids of live buffers
+    uint32_t per_stream = 1;        // slots per stream (slot k on stream k / per_stream)
 
-    explicit Fake(uint32_t slots) : state(slots, 0), slot_launch(slots, -1) {}
+    explicit Fake(uint32_t slots, uint32_t per = 1)
+        : state(slots, 0), slot_launch(slots, -1), per_stream(per) {}
 
     uint64_t fb_bytes(uint32_t w, uint32_t h) const override { return 4ull * w * h; }
     bool alloc_buf(uint32_t w, uint32_t h, FBuf& out) override {
@@ -78,6 +81,16 @@ struct Fake : Sched::Backend {
             l.sessions.push_back(it.req->session);
             l.clouds.push_back(it.req->cloud);
             l.steps.push_back(it.req->step);
+        }
+        // a cloud or session in flight on another stream is never launched
+        // (its steps would not be ordered); on the same stream it chains
+        for (uint32_t j = 0; j < state.size(); ++j) {
+            if (state[j] == 0 || j / per_stream == slot / per_stream) continue;
+            const Launched& o = log[slot_launch[j]];
+            for (uint32_t c : l.clouds)
+                CHECK(std::find(o.clouds.begin(), o.clouds.end(), c) == o.clouds.end());
+            for (uint32_t se : l.sessions)
+                CHECK(std::find(o.sessions.begin(), o.sessions.end(), se) == o.sessions.end());
         }
         log.push_back(l);
         if (k == fail_launch) return false;
@@ -249,16 +262,64 @@ void case_batches_overlap() {
     std::puts("ok batches_overlap");
 }
 
-// Random traffic: per cloud, steps go out in order and one at a time; per
+// Two slots per stream: clouds with deep queues chain their next steps into
+// the second slot of the stream they are in flight on, so every launch
+// carries all four; the idle stream takes nothing of theirs.
+void case_chain() {
+    Fake f(4, 2);
+    Sched s(f, 1ull << 40, 4, 64, 2);
+    std::vector<uint32_t> cl;
+    for (int k = 0; k < 4; ++k) cl.push_back(s.add_cloud());
+    std::vector<uint64_t> ids;
+    for (int round = 0; round < 6; ++round)
+        for (uint32_t k = 0; k < 4; ++k) ids.push_back(submit(s, k, cl[k]));
+    CHECK(s.schedule());  // steps 0 on stream 0
+    CHECK(s.schedule());  // steps 1 chained behind them on stream 0
+    CHECK(!s.schedule());  // stream 1 is free, but every cloud is in flight on stream 0
+    CHECK(f.log.size() == 2 && f.log[0].slot / 2 == 0 && f.log[1].slot / 2 == 0);
+    CHECK(f.log[0].ids.size() == 4 && f.log[1].ids.size() == 4);
+    f.state[f.log[0].slot] = 2;
+    CHECK(s.retire());
+    CHECK(s.schedule());  // steps 2 behind steps 1
+    CHECK(f.log.size() == 3 && f.log[2].slot == f.log[0].slot && f.log[2].ids.size() == 4);
+    drain(s, f);
+    std::map<uint32_t, uint32_t> next_step;
+    for (const Launched& l : f.log) {
+        CHECK(l.ids.size() == 4);
+        for (size_t k = 0; k < l.ids.size(); ++k) CHECK(l.steps[k] == next_step[l.clouds[k]]++);
+    }
+    const mm_server_stats st = s.stats();
+    CHECK(st.completed == ids.size() && st.launches == 6 && st.max_in_flight == 2);
+    s.free_all();
+    std::puts("ok chain");
+}
+
+// A request on a cloud with nothing in flight goes to an idle stream, beside
+// the launch in flight, not behind it.
+void case_independent_side_by_side() {
+    Fake f(4, 2);
+    Sched s(f, 1ull << 40, 4, 64, 2);
+    const uint32_t a = s.add_cloud(), b = s.add_cloud();
+    submit(s, 0, a);
+    CHECK(s.schedule());
+    submit(s, 1, b);
+    CHECK(s.schedule());
+    CHECK(f.log.size() == 2 && f.log[0].slot / 2 != f.log[1].slot / 2);
+    drain(s, f);
+    s.free_all();
+    std::puts("ok independent_side_by_side");
+}
+
+// Random traffic: per cloud, steps go out in order, on one stream at a time; per
 // launch, one request per session and per cloud; the budget is never
 // exceeded; every request completes; buffers are all freed at the end.
-void case_random(uint32_t seed) {
+void case_random(uint32_t seed, uint32_t per_stream) {
     std::mt19937 rng(seed);
-    const uint32_t slots = 1 + rng() % 3;
-    Fake f(slots);
+    const uint32_t slots = per_stream * (1 + rng() % 3);
+    Fake f(slots, per_stream);
     const uint32_t screens[3][2] = {{64, 64}, {128, 32}, {96, 96}};
     const uint64_t budget = (1 + rng() % 4) * f.fb_bytes(96, 96);
-    Sched s(f, budget, slots, 1 + rng() % 6);
+    Sched s(f, budget, slots, 1 + rng() % 6, per_stream);
     const uint32_t nclouds = 1 + rng() % 5, nsessions = 1 + rng() % 8;
     for (uint32_t c = 0; c < nclouds; ++c) s.add_cloud();
     std::vector<uint32_t> sess_screen(nsessions);
@@ -370,11 +431,15 @@ int main() {
     case_query_fails();
     case_alloc_fails();
     case_batches_overlap();
+    case_chain();
+    case_independent_side_by_side();
     case_close_session();
     case_evict_idle_first();
     case_drop_all();
-    for (uint32_t seed = 0; seed < 300; ++seed) case_random(seed);
+    for (uint32_t seed = 0; seed < 300; ++seed) case_random(seed, 1);
     std::puts("ok random x300");
+    for (uint32_t seed = 0; seed < 300; ++seed) case_random(seed, 2);
+    std::puts("ok random chained x300");
     std::puts("all ok");
     return 0;
 }
