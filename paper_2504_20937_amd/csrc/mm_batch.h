@@ -23,6 +23,7 @@ struct PlanView {
     uint32_t width = 0, height = 0;
     float view_proj[16] = {};
     bool full_clear = false;   // frame buffer holds no earlier frame of this view
+    uint32_t prev_stamp = 0;   // stamp of the frame buffer's previous frame (0: the previous launch's)
     uint32_t* colour = nullptr;
     bool owns_colour = false;
     // set by shape_views

@@ -165,6 +165,7 @@ mm_status build_tables(const std::vector<Cloud>& clouds, const std::vector<PlanV
         x.num_wg = v.num_wg;
         x.splits = v.splits;
         x.full_clear = v.full_clear ? 1u : 0u;
+        x.prev_stamp = v.prev_stamp;
         x.seed_lo = c.args.seed_lo;
         x.seed_hi = c.args.seed_hi;
         out.max_tiles = std::max(out.max_tiles, v.ntiles);

@@ -116,6 +116,9 @@ struct TileView {
     uint32_t tcol_stride;
     uint32_t full_clear; // 1: clear every tile not drawn this frame (the frame buffer
                          // holds no earlier frame); 0: only tiles drawn last frame
+    uint32_t prev_stamp; // non-zero: the stamp of the frame buffer's previous frame
+                         // (a served buffer, drawn by some earlier launch): tiles
+                         // drawn then and not now are cleared as well
     uint32_t seed_lo, seed_hi;
     Palette pal;
     uint32_t* hint;      // occlusion cull: the one-split 1x1 pass writes each drawn

@@ -37,6 +37,11 @@ struct FrameBuf {
     uint64_t* apron = nullptr;
     uint32_t* active = nullptr;
     bool fresh = false;    // new memory: its tile stamps are zeroed by its first launch
+    // Stamp of the launch that drew its frame (0: none, or the frame is not
+    // known to be whole). Every tile is then either drawn by that launch or
+    // clear, so the next frame clears only the tiles drawn then and not now
+    // instead of every tile it does not draw.
+    uint32_t last_stamp = 0;
 };
 
 struct SCloud {
@@ -170,6 +175,21 @@ bool mm_server_s::launch(uint32_t k, const std::vector<Sched::Item>& items) {
 }
 
 mm_status mm_server_s::launch_slot(Slot& sl, const std::vector<Sched::Item>& items) {
+    if (stamp + 1u == 0u) {
+        // every older stamp must read as "not this launch": once no launch
+        // reads them, clear all of them; each buffer's next frame then clears
+        // every tile it does not draw
+        for (hipStream_t st : streams) MM_HIP(hipStreamSynchronize(st));
+        mm_status st = MM_OK;
+        sched->for_each_buf([&](FrameBuf& b) {
+            const hipError_t e = hipMemset(b.active, 0, tiles_of(b.width, b.height, side) * 4);
+            if (e != hipSuccess && st == MM_OK) st = hip_fail(e, "server: resetting tile stamps");
+            b.last_stamp = 0;
+        });
+        MM_TRY(st);
+        stamp = 0;
+    }
+    const uint32_t launch_stamp = stamp + 1u;
     std::vector<mmb::Cloud> cl;
     std::vector<mmb::PlanView> views;
     for (const Sched::Item& it : items) {
@@ -186,7 +206,11 @@ mm_status mm_server_s::launch_slot(Slot& sl, const std::vector<Sched::Item>& ite
         v.width = r.width;
         v.height = r.height;
         std::memcpy(v.view_proj, r.m, sizeof v.view_proj);
-        v.full_clear = true;
+        // a request into the caller's buffer, a 3x3 footprint (whose edges
+        // the seam pass writes across tile borders) or a buffer without a
+        // known frame: every tile not drawn is cleared
+        v.full_clear = r.dev_out != nullptr || desc.footprint == 3 || buf.last_stamp == 0;
+        v.prev_stamp = v.full_clear ? 0u : buf.last_stamp;
         v.colour = r.dev_out ? r.dev_out : buf.colour;
         v.seg = c.seg;
         v.table = c.table;
@@ -231,20 +255,11 @@ mm_status mm_server_s::launch_slot(Slot& sl, const std::vector<Sched::Item>& ite
     // a kernel reads the staged tables: the slot's stream stays on the compute queue
     MM_HIP(mm::launch_upload(sl.dev, sl.pinned_dev, total, sl.stream));
     mmb::bind_args(sl.img, sl.dev, sl.dev + stat, sl.stamp_slot, shift, P, sl.b, sl.t, sl.m);
-    if (++stamp == 0) {
-        // every older stamp must read as "not this launch": clear all of them
-        // once every other launch has finished reading them
-        for (Slot& o : slots)
-            if (&o != &sl) MM_HIP(hipStreamSynchronize(o.stream));
-        mm_status st = MM_OK;
-        sched->for_each_buf([&](FrameBuf& b) {
-            const hipError_t e = hipMemset(b.active, 0, tiles_of(b.width, b.height, side) * 4);
-            if (e != hipSuccess && st == MM_OK) st = hip_fail(e, "server: resetting tile stamps");
-        });
-        MM_TRY(st);
-        stamp = 1;
-    }
+    stamp = launch_stamp;
     sl.b.stamp = stamp;
+    // the session's buffer now holds this frame, unless the frame went to the
+    // caller's buffer (the stamps then no longer describe the buffer's frame)
+    for (const Sched::Item& it : items) it.session->buf.last_stamp = it.req->dev_out ? 0u : stamp;
     sl.nodes = mmb::make_nodes(desc.domain, desc.footprint, shift, ppt, threads, sl.img,
                                desc.tuning.grid_blocks, &sl.b, &sl.t, &sl.m);
     for (const mmb::Node& n : sl.nodes) MM_HIP(mmh::launch(n.l, n.arg, sl.stream));

@@ -404,7 +404,7 @@ __global__ __launch_bounds__(kFusedThreads) void tile_fused_kernel(TileArgs a) {
     }
     const uint32_t stamp = *a.stamp_in, flag = tile_flag(a.v, t);
     if (flag != stamp) {
-        if (flag == stamp - 1u || a.v.full_clear) {
+        if (flag == stamp - 1u || (a.v.prev_stamp != 0u && flag == a.v.prev_stamp) || a.v.full_clear) {
             clear_tile<SHIFT>(a.v, t, threadIdx.x, kFusedThreads);
             if (a.v.hint)  // no winners now: no hints for the next frame
                 for (uint32_t q = threadIdx.x; q < S * S; q += kFusedThreads)
@@ -593,7 +593,8 @@ __global__ __launch_bounds__(kBatchThreads) void batch_tile_kernel(BatchTileArgs
         const bool resolve = FOOT == 1 && v.splits == 1u;
         const uint32_t flag = tile_flag(v, t);
         if (flag != stamp) {
-            if (resolve && (flag == stamp - 1u || v.full_clear))
+            if (resolve && (flag == stamp - 1u || (v.prev_stamp != 0u && flag == v.prev_stamp) ||
+                            v.full_clear))
                 clear_tile<SHIFT>(v, t, threadIdx.x, kBatchThreads);
             continue;
         }
@@ -625,7 +626,8 @@ __device__ __forceinline__ void merge_tile(const TileView& v, uint32_t t, uint32
     uint32_t* out = v.colour + static_cast<uint64_t>(y0) * v.width + x0;
     const uint32_t flag = tile_flag(v, t);
     if (flag != stamp) {
-        if (flag == stamp - 1u || v.full_clear) clear_tile<SHIFT>(v, t, tid, step);
+        if (flag == stamp - 1u || (v.prev_stamp != 0u && flag == v.prev_stamp) || v.full_clear)
+            clear_tile<SHIFT>(v, t, tid, step);
         return;
     }
     // the tile's partial blocks: its pieces, or its `splits` static splits

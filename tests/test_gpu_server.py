@@ -232,6 +232,50 @@ def test_server_frame_buffer_holds_the_last_request(rig):
     mm.mm_destroy_server(srv)
 
 
+def test_server_session_frames_clear_what_the_last_frame_drew(rig):
+    """A session's frame buffer clears only the tiles its previous frame drew
+    and this one does not. A dense cloud (60,000 points) and a sparse one
+    (12 points) alternate in one session's buffer, so most tiles go from
+    drawn to clear and back. With a budget of one buffer, two sessions of one
+    screen then hand the buffer back and forth through the pool, each frame
+    drawn over the other session's. Every frame is read back and compared
+    with the oracle's."""
+    mm = rig.mm
+    say("case: server, session frames over dense and sparse clouds, one-buffer pool")
+    clouds = _clouds(rig, [60000, 12])
+    refs = [c[0].copy() for c in clouds]
+    steps = [0, 0]
+
+    def serve(srv, s, c, f, w, h, deg):
+        cam = synth.orbit_camera(f, w, h, start_deg=deg)
+        r = mm.mm_server_submit(srv, s, c, cam, w, h)
+        mm.mm_server_wait(srv, r)
+        _, _, _, seed, amp = clouds[c]
+        oracle.displace(refs[c], seed, steps[c], amp, False)
+        steps[c] += 1
+        want = oracle.render(refs[c], seed, cam, w, h, 1)
+        got = mm.mm_server_read_frame(srv, s, w, h)
+        assert np.array_equal(got, want), f"session {s} cloud {c} frame {f}: {first_diff(got, want)}"
+
+    srv = mm.mm_create_server(rig.inst, 1 << 32, 2, 4, 3, 1)
+    for c in clouds:
+        mm.mm_server_add_cloud(srv, mm.make_cloud_desc(c[2], c[0].shape[0], 3, c[3], c[4]))
+    for f, c in enumerate([0, 1, 1, 0, 1, 0, 0, 1]):
+        serve(srv, 0, c, f, 320, 200, 30.0)
+    mm.mm_destroy_server(srv)
+    # one 256x192 frame buffer (under 1 MB with its tile scratch) fits the budget, two do not;
+    # a new server counts each cloud's steps from 0 again (on the positions reached so far)
+    steps[:] = [0, 0]
+    srv = mm.mm_create_server(rig.inst, 1 << 20, 1, 4, 3, 1)
+    for c in clouds:
+        mm.mm_server_add_cloud(srv, mm.make_cloud_desc(c[2], c[0].shape[0], 3, c[3], c[4]))
+    for f in range(6):
+        serve(srv, f % 2, f % 2, 8 + f, 256, 192, 60.0 * (f % 2))
+    st = mm.mm_server_stats_get(srv)
+    assert st["evictions"] >= 4 and st["admitted_sessions"] == 1, st
+    mm.mm_destroy_server(srv)
+
+
 def test_server_3x3_footprint(rig):
     say("case: server, 3x3 footprint, 3 clouds, 4 sessions, 20 requests")
     clouds = _clouds(rig, [40000, 9000, 120000])
