@@ -46,7 +46,7 @@ KERNEL_SOURCES = {
 TRAFFIC = {
     "bin_kernel": {"workload": "3d-uniform-2^24pts-1920x1080-orbit-1deg",
                    "tuning": [2, 32, 8, 1, 1024, 0xFFFFFFFF, 2],
-                   "digest": "94b7f6d8371b4f5e", "fetch_kib": 98395.0, "write_kib": 335980.7,
+                   "digest": "6d0bd9d98184e02d", "fetch_kib": 98394.9, "write_kib": 335988.3,
                    "fetch_scale": 2.0, "write_scale": 1.0},
 }
 FRAMES_PER_LAUNCH = 1  # frames per graph launch: the workload is one hipGraph per frame
