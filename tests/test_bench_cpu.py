@@ -54,3 +54,17 @@ def test_traffic_counters_match_the_current_kernel_sources():
     assert b.measured_traffic("bin_kernel", "another-workload", e["tuning"]) is None
     assert b.measured_traffic("bin_kernel", e["workload"], [2, 64, 8, 1, 1024, 0, 2]) is None
     assert b.measured_traffic("bin_kernel", e["workload"], e["tuning"][:6] + [1]) is None
+
+
+def test_cobound_probe_rejects_arguments_before_any_device_call():
+    """The co-bound microbenchmark checks its arguments first: out-of-range
+    sizes or launch counts end with status 2 and its usage line, with no
+    device touched (this container has none)."""
+    import pytest
+    exe = os.path.join(ROOT, "paper_2504_20937_amd", "mm_cobound")
+    if not os.path.exists(exe):
+        pytest.skip("mm_cobound is not built")
+    for args in (["12"], ["31"], ["24", "0"], ["24", "10001"]):
+        r = subprocess.run([exe, *args], capture_output=True, text=True, timeout=60)
+        assert r.returncode == 2, (args, r.returncode, r.stderr)
+        assert "usage: mm_cobound" in r.stderr, r.stderr
