@@ -274,6 +274,28 @@ def test_server_session_frames_clear_what_the_last_frame_drew(rig):
     st = mm.mm_server_stats_get(srv)
     assert st["evictions"] >= 4 and st["admitted_sessions"] == 1, st
     mm.mm_destroy_server(srv)
+    # a frame into the caller's buffer between two into the session's own: the
+    # session's buffer still holds the frame before it, so the frame after it
+    # clears every tile it does not draw
+    steps[:] = [0, 0]
+    torch = rig.torch
+    srv = mm.mm_create_server(rig.inst, 1 << 32, 2, 4, 3, 1)
+    for c in clouds:
+        mm.mm_server_add_cloud(srv, mm.make_cloud_desc(c[2], c[0].shape[0], 3, c[3], c[4]))
+    serve(srv, 3, 0, 20, 200, 160, 10.0)
+    out = torch.zeros((160, 200), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    cam = synth.orbit_camera(21, 200, 160, start_deg=10.0)
+    mm.mm_server_wait(srv, mm.mm_server_submit(srv, 3, 1, cam, 200, 160, out.data_ptr()))
+    _, _, _, seed, amp = clouds[1]
+    oracle.displace(refs[1], seed, steps[1], amp, False)
+    steps[1] += 1
+    got = out.cpu().numpy().view(np.uint32)
+    want = oracle.render(refs[1], seed, cam, 200, 160, 1)
+    assert np.array_equal(got, want), f"frame into the caller's buffer: {first_diff(got, want)}"
+    serve(srv, 3, 1, 22, 200, 160, 10.0)
+    serve(srv, 3, 0, 23, 200, 160, 10.0)
+    mm.mm_destroy_server(srv)
 
 
 def test_server_3x3_footprint(rig):
